@@ -1,0 +1,211 @@
+"""Algorithms 1 and 2 with explicit per-box loops (oracle; test infrastructure).
+
+* ``build``  -- Algorithm 1 (Sec. 4.2): leaves by Sec. 3; parents by the merge
+  of Sec. 4: X = (T33a - T33b)^-1, S = X [-T31a | T32b],
+  T = blkdiag(T11a, T22b) + [T13a; T23b] S.  A refined box whose side faces an
+  unrefined same-size leaf gets T <- P_down T P_up (Sec. 5.3); S is kept and
+  P_up applied in the solve (S_new = S P_up).
+* ``solve``  -- Algorithm 2 (Sec. 4.3): upward pass h = H g at leaves,
+  w = X(h3b - h3a), h = [h1a; h2b] + [T13a; T23b] w at parents (h <- P_down h
+  on coarsened boxes, Sec. 5.4); downward pass u(root boundary) = f,
+  u_gi = S u_ge + w at parents (u_ge,fine = P_up u_ge first, Sec. 5.4),
+  u_c = S u_ge + F g at leaves.
+* ``solve_adjoint`` -- the transpose of the linear map (f, g) -> u_c of
+  Algorithm 2, taken step by step in reverse order (not in the paper).
+* ``coeff_gradient`` -- dL/dc for the nodal coefficients: with lambda the
+  adjoint of the collocation system, only the PDE rows depend on c, so
+  dL/dc_k(i) = -gbar(i) * (B_k u)(i) at interior nodes, with B_k the operator
+  multiplying c_k in A (Sec. 3.2); zero at exterior nodes.
+
+Explicit inverses use LAPACK getrf/getrs (scipy.linalg.lu_factor/lu_solve).
+"""
+
+import numpy as np
+import scipy.linalg as sla
+
+from .leaf import leaf_operators
+
+
+class Ops:
+    pass
+
+
+def _inv(Z):
+    lu = sla.lu_factor(Z)
+    if np.any(np.diag(lu[0]) == 0.0):
+        raise np.linalg.LinAlgError("singular interface block")
+    return sla.lu_solve(lu, np.eye(Z.shape[0]))
+
+
+def _merge_index(tau):
+    a, b = tau.alpha, tau.beta
+    pa = {j: i for i, j in enumerate(a.ge)}
+    pb = {j: i for i, j in enumerate(b.ge)}
+    sb = set(b.ge)
+    sa = set(a.ge)
+    p3a = [pa[j] for j in tau.gi]
+    p3b = [pb[j] for j in tau.gi]
+    p1a = [pa[j] for j in a.ge if j not in sb]
+    p2b = [pb[j] for j in b.ge if j not in sa]
+    return np.array(p1a, int), np.array(p2b, int), np.array(p3a, int), np.array(p3b, int)
+
+
+def build(tree, coeffs, p, q=None):
+    """Algorithm 1.  coeffs: [n_leaves, 6, p*p] in canonical leaf order."""
+    if q is None:
+        q = p - 1
+    tree.gauss(q)
+    leaves = tree.leaves
+    leaf_pos = {b.id: i for i, b in enumerate(leaves)}
+    ops = Ops()
+    ops.tree, ops.p, ops.q = tree, p, q
+    ops.box = {}
+    for tau in reversed(tree.boxes):                 # tau = N_boxes, ..., 1
+        if tau.is_leaf:
+            o = leaf_operators(tree.box_phys(tau), coeffs[leaf_pos[tau.id]], p, q)
+            ops.box[tau.id] = o
+            continue
+        oa, ob = ops.box[tau.alpha.id], ops.box[tau.beta.id]
+        p1a, p2b, p3a, p3b = _merge_index(tau)
+        Ta, Tb = oa["T"], ob["T"]
+        X = _inv(Ta[np.ix_(p3a, p3a)] - Tb[np.ix_(p3b, p3b)])
+        R = np.hstack([-Ta[np.ix_(p3a, p1a)], Tb[np.ix_(p3b, p2b)]])
+        S = X @ R
+        n1, n2 = p1a.size, p2b.size
+        T = np.zeros((n1 + n2, n1 + n2))
+        T[:n1, :n1] = Ta[np.ix_(p1a, p1a)]
+        T[n1:, n1:] = Tb[np.ix_(p2b, p2b)]
+        Q = np.vstack([Ta[np.ix_(p1a, p3a)], Tb[np.ix_(p2b, p3b)]])
+        T = T + Q @ S
+        o = dict(X=X, S=S, Q=Q, T_fine=T, idx=(p1a, p2b, p3a, p3b))
+        if tau.Pup is not None:
+            o["T"] = tau.Pdown @ T @ tau.Pup
+        else:
+            o["T"] = T
+        ops.box[tau.id] = o
+    ops.leaf_pos = leaf_pos
+    return ops
+
+
+def solve(ops, f, g):
+    """Algorithm 2 for one right-hand side.
+
+    f: [n_bdry] Dirichlet data at the canonical boundary Gauss nodes;
+    g: [n_leaves, (p-2)^2] body load at leaf interior Chebyshev nodes.
+    Returns (u_c [n_leaves, p*p], u [N] at every Gauss node).
+    """
+    tree, p, q = ops.tree, ops.p, ops.q
+    node_xy, bdry = tree.gauss(q)
+    boxes = tree.boxes
+    h = {}
+    w = {}
+    for tau in reversed(boxes):                      # upward pass
+        o = ops.box[tau.id]
+        if tau.is_leaf:
+            h[tau.id] = o["H"] @ g[ops.leaf_pos[tau.id]]
+            continue
+        p1a, p2b, p3a, p3b = o["idx"]
+        ha, hb = h[tau.alpha.id], h[tau.beta.id]
+        w[tau.id] = o["X"] @ (-ha[p3a] + hb[p3b])
+        hf = np.concatenate([ha[p1a], hb[p2b]]) + o["Q"] @ w[tau.id]
+        h[tau.id] = tau.Pdown @ hf if tau.Pdown is not None else hf
+    u = np.zeros(node_xy.shape[0])
+    u[bdry] = f
+    u_c = np.zeros((len(tree.leaves), p * p))
+    for tau in boxes:                                # downward pass
+        o = ops.box[tau.id]
+        if tau.Pup is not None:
+            u[tau.ge_fine] = tau.Pup @ u[tau.ge]
+        ge = tau.ge_fine if tau.ge_fine is not None else tau.ge
+        if tau.is_leaf:
+            i = ops.leaf_pos[tau.id]
+            u_c[i] = o["S"] @ u[ge] + o["F"] @ g[i]
+        else:
+            u[tau.gi] = o["S"] @ u[ge] + w[tau.id]
+    return u_c, u
+
+
+def solve_adjoint(ops, ubar_c):
+    """Transpose of (f, g) -> u_c.  ubar_c: [n_leaves, p*p].
+
+    Returns (fbar [n_bdry], gbar [n_leaves, (p-2)^2]).
+    """
+    tree, p, q = ops.tree, ops.p, ops.q
+    node_xy, bdry = tree.gauss(q)
+    boxes = tree.boxes
+    N = node_xy.shape[0]
+    mi = (p - 2) ** 2
+    gbar = np.zeros((len(tree.leaves), mi))
+    ubar = np.zeros(N)
+    wbar = {}
+    # reverse of the downward pass: children before parents
+    for tau in reversed(boxes):
+        o = ops.box[tau.id]
+        ge = tau.ge_fine if tau.ge_fine is not None else tau.ge
+        if tau.is_leaf:
+            i = ops.leaf_pos[tau.id]
+            np.add.at(ubar, ge, o["S"].T @ ubar_c[i])
+            gbar[i] += o["F"].T @ ubar_c[i]
+        else:
+            ugi = ubar[tau.gi].copy()
+            ubar[tau.gi] = 0.0
+            wbar[tau.id] = ugi
+            np.add.at(ubar, ge, o["S"].T @ ugi)
+        if tau.Pup is not None:
+            # u[fine] = P_up u[coarse] overwrote the slave entries
+            coarse = set(tau.ge)
+            slaves = [k for k, j in enumerate(tau.ge_fine) if j not in coarse]
+            sl_ids = [tau.ge_fine[k] for k in slaves]
+            ub_s = ubar[sl_ids].copy()
+            ubar[sl_ids] = 0.0
+            np.add.at(ubar, tau.ge, tau.Pup[slaves].T @ ub_s)
+    fbar = ubar[bdry].copy()
+    # reverse of the upward pass: parents before children
+    hbar = {tau.id: None for tau in boxes}
+    for tau in boxes:
+        o = ops.box[tau.id]
+        hb = hbar[tau.id]
+        if tau.is_leaf:
+            if hb is not None:
+                gbar[ops.leaf_pos[tau.id]] += o["H"].T @ hb
+            continue
+        a, b = tau.alpha, tau.beta
+        p1a, p2b, p3a, p3b = o["idx"]
+        wb = wbar[tau.id].copy()
+        ha = np.zeros(len(a.ge))
+        hbb = np.zeros(len(b.ge))
+        if hb is not None:
+            hf = tau.Pdown.T @ hb if tau.Pdown is not None else hb
+            n1 = p1a.size
+            ha[p1a] += hf[:n1]
+            hbb[p2b] += hf[n1:]
+            wb += o["Q"].T @ hf
+        d = o["X"].T @ wb
+        ha[p3a] -= d
+        hbb[p3b] += d
+        hbar[a.id] = ha
+        hbar[b.id] = hbb
+    return fbar, gbar
+
+
+def coeff_gradient(ops, u_c, gbar):
+    """dL/dc_k at every leaf node, [n_leaves, 6, p*p] (k = c11, c12, c22,
+    c1, c2, c); exterior nodes get zero."""
+    tree, p = ops.tree, ops.p
+    out = np.zeros((len(tree.leaves), 6, p * p))
+    for tau in tree.leaves:
+        i = ops.leaf_pos[tau.id]
+        o = ops.box[tau.id]
+        from .leaf import leaf_geometry, reference_matrices
+        x0, x1, y0, y1 = tree.box_phys(tau)
+        D, _, _ = reference_matrices(p, ops.q)
+        Ip = np.eye(p)
+        D1 = np.kron(Ip, (2.0 / (x1 - x0)) * D)
+        D2 = np.kron((2.0 / (y1 - y0)) * D, Ip)
+        u = u_c[i]
+        Bu = [-(D1 @ (D1 @ u)), -2.0 * (D1 @ (D2 @ u)), -(D2 @ (D2 @ u)),
+              D1 @ u, D2 @ u, u]
+        I_ci = o["I_ci"]
+        for k in range(6):
+            out[i, k, I_ci] = -gbar[i] * Bu[k][I_ci]
+    return out
