@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Benchmark: HPS factor + solve on one MI355X.
+
+Workload: the full variable-coefficient operator
+  c11 = 1 + .5 sin(2 pi x) cos(2 pi y), c22 = 1 + .3 cos(2 pi x),
+  c12 = .1 sin(pi x) sin(pi y), c1 = c2 = .5 sin(2 pi y), c = 1 + x^2
+on [0,1]^2 with 64 x 64 leaves, p = 16, q = 15 (N = p^2 n^2 = 1,048,576
+collocation nodes), body loads and boundary data of 32 seeded manufactured
+solutions (sums of 8 Fourier modes, seeds 2..33).  Synthetic data, inputs
+resident in device memory before timing.
+
+One step = Algorithm 1 (hps_refactor on the resident coefficients) followed by
+Algorithm 2 for the batch of 32 right-hand sides in FP64.  value = right-hand
+sides solved per second of whole steps (factor included).  Separately
+reported: factor time, solve-only throughput at nrhs 32 and 1, achieved
+TFLOP/s, relative error against stored oracle values, the roofline of the
+dominant kernel (from HIP events around its launches inside the timed steps)
+and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_LEAF_SIDE, P, Q, NRHS = 64, 16, 15, 32
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector = FP64 matrix
+
+
+def make_inputs(tree, nrhs, p=P, q=Q):
+    import workloads as W
+    xy = tree.leaf_cheb_nodes(p)
+    X, Y = xy[..., 0], xy[..., 1]
+    coeffs = np.transpose(W.varcoeff(X, Y), (1, 0, 2)).copy()     # [nl, 6, p^2]
+    pi = p - 2
+    ii = np.array([(iy + 1) * p + ix + 1 for iy in range(pi) for ix in range(pi)])
+    Xi, Yi = X[:, ii], Y[:, ii]
+    ci = coeffs[:, :, ii].transpose(1, 0, 2)
+    b = tree.bdry_gauss_nodes(q)
+    fs, gs = [], []
+    for r in range(nrhs):
+        sol = W.FourierSolution(2 + r)
+        gs.append(sol.g(Xi, Yi, ci))
+        fs.append(sol.u(b[:, 0], b[:, 1]))
+    return (np.ascontiguousarray(coeffs), np.ascontiguousarray(np.stack(fs)),
+            np.ascontiguousarray(np.stack(gs)))
+
+
+def flop_model(H, solver):
+    """Algorithmic flops of Algorithm 1 as implemented (explicit inverses by
+    Gauss-Jordan = 2 n^3) and operator bytes read by one solve."""
+    from paper_1612_02736_amd.hps import debug_boxes
+    boxes = debug_boxes(solver)
+    mi, me, g4 = (P - 2) ** 2, 4 * (P - 1), 4 * Q
+    leaf_inv = 2.0 * mi ** 3
+    leaf_gemm = 2.0 * mi * me * g4 + 4.0 * mi * mi * g4 + 2.0 * g4 * g4 * mi
+    nleaf = int(np.sum(boxes[:, 0] == 1))
+    merge_inv = merge_gemm = 0.0
+    merge_words = 0.0
+    for info in boxes:
+        if info[0]:
+            continue
+        m, en = float(info[7]), float(info[6])
+        merge_inv += 2.0 * m ** 3
+        merge_gemm += 2.0 * m * m * en + (2.0 * en * en * m if info[2] >= 0 else 0.0)
+        merge_words += m * m + m * en + (en * m if info[2] >= 0 else 0.0)
+    leaf_words = nleaf * (mi * (g4 + mi) + g4 * mi + me * g4 / nleaf)
+    return dict(leaf_inv=nleaf * leaf_inv, leaf_gemm=nleaf * leaf_gemm,
+                merge_inv=merge_inv, merge_gemm=merge_gemm,
+                build=nleaf * (leaf_inv + leaf_gemm) + merge_inv + merge_gemm,
+                solve_bytes=8.0 * (leaf_words + merge_words), nleaf=nleaf)
+
+
+def cpu_baseline(nrhs):
+    """The oracle as it stands, on a 16 x 16-leaf sample of the same p = 16
+    problem (256 of the 4096 leaves), scaled by the leaf-count ratio 16."""
+    from threadpoolctl import threadpool_info
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    import workloads as W
+    from oracle_cases import make_inputs as oracle_inputs
+    n = 16
+    t = oracle.Tree.uniform(0.0, 1.0, 0.0, 1.0, n, n)
+    coeffs, f, g, _ = oracle_inputs(t, P, Q, W.varcoeff, W.FourierSolution(2))
+    t0 = time.perf_counter()
+    ops = oracle.build(t, coeffs, P, Q)
+    t1 = time.perf_counter()
+    oracle.solve(ops, f, g)
+    t2 = time.perf_counter()
+    scale = (N_LEAF_SIDE * N_LEAF_SIDE) / (n * n)
+    t_build, t_solve = (t1 - t0) * scale, (t2 - t1) * scale
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": nrhs / (t_build + nrhs * t_solve), "unit": "solves/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": (f"oracle build + 1 solve on 16x16 leaves of the same p=16 problem "
+                       f"({t1 - t0:.1f} s + {t2 - t1:.2f} s), scaled x{scale:.0f} to 64x64; "
+                       f"step = factor + {nrhs} solves"),
+            "factor_s_scaled": t_build, "solve_s_scaled": t_solve}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=NRHS)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1612_02736_amd as H
+    from paper_1612_02736_amd.hps import debug_profile, debug_profile_read
+    H.lib()
+    dev = torch.device("cuda:0")
+    tree = H.Tree(0.0, 1.0, 0.0, 1.0, N_LEAF_SIDE, N_LEAF_SIDE)
+    coeffs, f, g = make_inputs(tree, args.nrhs)
+    cd = torch.from_numpy(coeffs).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    gd = torch.from_numpy(g).to(dev)
+    solver = H.Solver(tree, cd, P, Q)
+    fm = flop_model(H, solver)
+    for _ in range(args.warmup):
+        solver.refactor(cd)
+        u = solver.solve(fd, gd)
+    torch.cuda.synchronize()
+    debug_profile(solver, True)
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        solver.refactor(cd)
+        e1.record()
+        u = solver.solve(fd, gd)
+        e2.record()
+        ev.append((e0, e1, e2))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = debug_profile_read(solver)
+    debug_profile(solver, False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    factor_ms = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
+    solve32_ms = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
+    # solve-only throughput at nrhs = 1 (outside the timed steps)
+    f1, g1 = fd[:1].contiguous(), gd[:1].contiguous()
+    solver.solve(f1, g1)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for _ in range(10):
+        solver.solve(f1, g1)
+    torch.cuda.synchronize()
+    solve1_ms = (time.perf_counter() - s0) * 1e2
+    # accuracy against stored oracle values (seed 2 = right-hand side 0)
+    rel_err = None
+    ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
+    if os.path.exists(ref):
+        z = np.load(ref, allow_pickle=False)
+        ug = u[0].cpu().numpy()[z["leaves"]]
+        rel_err = float(np.max(np.abs(ug - z["u"])) / np.max(np.abs(z["u"])))
+    # dominant kernel from the per-launch events of the timed steps
+    agg = {}
+    for kind, var, ms in prof:
+        agg.setdefault((kind, var), []).append(ms)
+    per_step = {k: sum(v) / args.steps for k, v in agg.items()}
+    dom = max(per_step, key=per_step.get)
+    launches = len(agg[dom]) / args.steps
+    avg_ms = sum(agg[dom]) / len(agg[dom])
+    if dom == ("gj_leaf", 0):
+        algo = fm["leaf_inv"]
+        roof = {"bound": "alu", "achieved": algo / (avg_ms * 1e-3) / 1e12,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    elif dom[0] == "apply":
+        algo = fm["solve_bytes"] / max(launches, 1)
+        roof = {"bound": "hbm", "achieved": algo / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        algo = fm["leaf_gemm"] / max(launches, 1)
+        roof = {"bound": "mfma", "achieved": algo / (avg_ms * 1e-3) / 1e12,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"{dom[0]}[{dom[1]}]"
+    roof["avg_launch_ms"] = avg_ms
+    out = {
+        "metric": "factor s + solves/s at N≈1M p=16 (FP64 vs mixed); TFLOP/s, rel err vs FP64",
+        "value": args.nrhs * 1e3 / ms_step,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "variable-coefficient A on [0,1]^2, 64x64 leaves, p=16, q=15, "
+                               "N=1,048,576, 32 RHS per step (factor + FP64 solve)",
+                   "leaves": fm["nleaf"], "p": P, "q": Q, "nrhs": args.nrhs,
+                   "parallelism": "single GPU"},
+        "factor_s": factor_ms * 1e-3,
+        "build_tflops": fm["build"] / (factor_ms * 1e-3) / 1e12,
+        "build_gflop": fm["build"] / 1e9,
+        "solve_ms_fp64_nrhs32": solve32_ms,
+        "solves_per_s_fp64_nrhs32": args.nrhs * 1e3 / solve32_ms,
+        "solve_ms_fp64_nrhs1": solve1_ms,
+        "solves_per_s_fp64_nrhs1": 1e3 / solve1_ms,
+        "solve_operator_gb": fm["solve_bytes"] / 1e9,
+        "rel_err_vs_oracle": rel_err,
+        "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.nrhs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

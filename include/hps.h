@@ -1,0 +1,183 @@
+/*
+ * hps.h -- C ABI of the MI355X Hierarchical Poincare-Steklov (HPS) direct
+ * solver: build (factor) and solve stages for
+ *
+ *     A u = g in Omega,  u = f on Gamma = boundary of Omega,
+ *     A u = -c11 u_xx - 2 c12 u_xy - c22 u_yy + c1 u_x + c2 u_y + c u,
+ *
+ * on a rectangle Omega split into a binary tree of boxes whose leaves carry
+ * a p x p Chebyshev grid and q Gauss nodes per side (Babb, Gillman, Hao,
+ * Martinsson, arXiv:1612.02736: problem statement eqs. basic/defA, leaf
+ * discretisation Sec. 3, merge Sec. 4, Algorithms 1 and 2, local refinement
+ * Sec. 5).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: HPS_OK (0) or a negative HPS_E* code; a thread-local text
+ *    explaining the last failure is available from hps_last_error().  No C++
+ *    exception crosses this interface.
+ *  - Floating point arrays are IEEE binary64 unless stated.  "host" arrays
+ *    live in ordinary CPU memory; "device" arrays are HIP device pointers on
+ *    the current device (for example torch CUDA tensors).  The caller owns
+ *    every array it passes; the library never frees or keeps them.
+ *  - Leaf order ("canonical"): leaves sorted by (problem, y0, x0).
+ *  - Chebyshev grid of a leaf: node (ix, iy), 0 <= ix, iy < p, has index
+ *    iy*p + ix; coordinates ascend.  Interior nodes 1 <= ix, iy <= p-2 are
+ *    numbered (iy-1)*(p-2) + (ix-1).
+ *  - Domain boundary Gauss nodes of a problem ("canonical"): sides S, E, N, W
+ *    in that order, each in increasing coordinate; problems one after
+ *    another.
+ *  - Boundary flux convention of the paper (Sec. 3.1): +d/dx on vertical
+ *    sides and +d/dy on horizontal sides.
+ *  - Multiple right-hand sides are stored one after another ("RHS-major").
+ *  - Work is enqueued on the HIP stream given in the options (0 = the null
+ *    stream) and the calls return after the stream has drained, unless
+ *    stated otherwise.
+ */
+#ifndef HPS_H
+#define HPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HPS_OK = 0,
+  HPS_EINVAL = -1,      /* bad argument (size, pointer, q >= p, nrhs <= 0) */
+  HPS_ETREE = -2,       /* malformed tree (non-dyadic split, bad problem) */
+  HPS_ESINGULAR = -3,   /* zero pivot in a leaf or interface block */
+  HPS_ENONFINITE = -4,  /* NaN/Inf met in a pivot */
+  HPS_ENOCONV = -5,     /* iterative refinement missed its tolerance */
+  HPS_EHIP = -6,        /* a HIP runtime call failed */
+  HPS_ENOMEM = -7       /* device or host allocation failed */
+};
+
+typedef struct hps_tree hps_tree;
+typedef struct hps_handle hps_handle;
+
+typedef struct {
+  int n_problems;
+  int n_leaves;          /* all problems together */
+  int n_boxes;           /* leaves + merges, all problems */
+  int n_levels;          /* distinct merge heights */
+  int max_depth;         /* deepest refinement level below the base grid */
+} hps_tree_info_t;
+
+/* Options of hps_build; pass NULL for the defaults. */
+typedef struct {
+  int q;                 /* Gauss nodes per leaf side; 0 -> p - 1 */
+  void *stream;          /* hipStream_t; 0 -> null stream */
+  int keep_fp32;         /* 1: also keep FP32 copies of the solve operators
+                            (needed for HPS_PREC_MIXED solves) */
+} hps_build_opts;
+
+enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
+
+/* Options of hps_solve / hps_solve_adjoint; pass NULL for the defaults. */
+typedef struct {
+  int precision;         /* HPS_PREC_*; MIXED = FP32 sweeps + FP64 residual
+                            iterative refinement */
+  double ir_tol;         /* MIXED: stop when max|du| <= ir_tol * max|u| */
+  int max_iter;          /* MIXED: refinement steps (0 -> 6) */
+  void *stream;          /* hipStream_t; 0 -> null stream */
+  double *u_gauss;       /* optional device out [nrhs][n_gauss] */
+  int *iters_out;        /* optional host out: refinement steps taken */
+  double *resid_out;     /* optional host out: last max|du|/max|u| */
+} hps_solve_opts;
+
+/* -- trees (host objects) ------------------------------------------------- */
+
+/* A forest of n_problems copies of [x0,x1] x [y0,y1], each split into a
+ * uniform nx x ny grid of leaf boxes (Sec. 2, Fig. 1).  A box covering
+ * several leaves is cut across the direction with more leaves (x on ties);
+ * the west/south part is child alpha.  Returns HPS_EINVAL for non-positive
+ * sizes or an empty rectangle. */
+int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
+                     int ny, int n_problems, hps_tree **out);
+
+/* Sec. 5.1: n_ref rounds of splitting into 2 x 2 every leaf of problem
+ * `problem` whose distance to (px, py) is <= t * (half its side); t = sqrt(2)
+ * in the paper.  Must be called before hps_build; invalidates earlier
+ * node queries. */
+int hps_tree_refine_point(hps_tree *tree, int problem, double px, double py,
+                          int n_ref, double t);
+
+int hps_tree_info(const hps_tree *tree, hps_tree_info_t *info);
+
+/* Number of Gauss nodes for a given q: all nodes, and those on the domain
+ * boundary (the length of f per right-hand side). */
+int hps_tree_counts(const hps_tree *tree, int q, int64_t *n_gauss,
+                    int64_t *n_bdry);
+
+/* host out [n_leaves][p*p][2]: (x, y) of every leaf Chebyshev node. */
+int hps_leaf_cheb_nodes(const hps_tree *tree, int p, double *xy);
+
+/* host out [n_leaves][4]: x0, x1, y0, y1 of every leaf. */
+int hps_leaf_boxes(const hps_tree *tree, double *boxes);
+
+/* host out [n_bdry][2]: canonical boundary Gauss nodes. */
+int hps_bdry_gauss_nodes(const hps_tree *tree, int q, double *xy);
+
+/* host out [n_gauss][2]: every Gauss node in the order of u_gauss. */
+int hps_gauss_nodes(const hps_tree *tree, int q, double *xy);
+
+void hps_tree_free(hps_tree *tree);
+
+/* -- build stage (Algorithm 1) -------------------------------------------- */
+
+/* coeffs: device [n_leaves][6][p*p], nodal c11, c12, c22, c1, c2, c.
+ * Builds F, S, H, T on every leaf (Sec. 3) and X, S, T on every merge
+ * (Sec. 4), with P_up/P_down on refined interfaces (Sec. 5.3).  The handle
+ * owns the operators (device memory) and keeps a copy of the tree.
+ * Errors: HPS_EINVAL (p < 4, q < 2, q >= p, NULL), HPS_ESINGULAR (message
+ * names the first failing box), HPS_ENONFINITE, HPS_EHIP, HPS_ENOMEM.  On
+ * failure *out is NULL. */
+int hps_build(const hps_tree *tree, const double *coeffs, int p,
+              const hps_build_opts *opts, hps_handle **out);
+
+/* Algorithm 1 again on an existing handle for new coefficients (same tree,
+ * p, q and layouts as hps_build): no device memory is allocated, the stored
+ * operators are overwritten.  stream: hipStream_t (0 = null stream).
+ * Errors as hps_build; on failure the handle's operators are undefined until
+ * a successful refactor. */
+int hps_refactor(hps_handle *h, const double *coeffs, void *stream);
+
+/* Device bytes the operators of a build take (FP64 only). */
+size_t hps_build_workspace_size(const hps_tree *tree, int p, int q);
+
+/* -- solve stage (Algorithm 2) -------------------------------------------- */
+
+/* f: device [nrhs][n_bdry] (canonical boundary order);
+ * g: device [nrhs][n_leaves][(p-2)^2] (interior Chebyshev nodes);
+ * u: device out [nrhs][n_leaves][p*p].
+ * Upward pass h = H g, w = X(h3b - h3a), h = [h1a; h2b] + [T13a; T23b] w;
+ * downward pass u_gi = S u_ge + w, u_c = S u_ge + F g (Algorithm 2). */
+int hps_solve(hps_handle *h, const double *f, const double *g, int nrhs,
+              double *u, const hps_solve_opts *opts);
+
+/* Transpose of the linear map (f, g) -> u_c of hps_solve (not in the
+ * paper): given ubar [nrhs][n_leaves][p*p] (device) returns
+ * fbar [nrhs][n_bdry] and gbar [nrhs][n_leaves][(p-2)^2] (device) by the
+ * transposed sweeps, reusing the stored operators. */
+int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs,
+                      double *fbar, double *gbar, const hps_solve_opts *opts);
+
+/* dL/dc for the zeroth-order coefficient c from the adjoint load gbar and the
+ * forward solution u (both device, layouts as above):
+ * cbar [nrhs][n_leaves][p*p] = -gbar * u on interior nodes, 0 on exterior
+ * nodes (only the collocated PDE rows depend on c). */
+int hps_coeff_grad_c(hps_handle *h, const double *u, const double *gbar,
+                     int nrhs, double *cbar, void *stream);
+
+void hps_handle_free(hps_handle *h);
+
+/* Thread-local description of the last failure on this thread. */
+const char *hps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPS_H */

@@ -1,0 +1,12 @@
+"""MI355X-native HPS (Hierarchical Poincare-Steklov) direct solver.
+
+The solver lives in the HIP/C++ library ``libhps.so`` (C ABI in
+``include/hps.h``); ``hps`` is its ctypes binding and ``autograd`` wraps the
+solve and its adjoint as a ``torch.autograd.Function``.
+"""
+
+from .hps import (HPS_PREC_FP32, HPS_PREC_FP64, HPS_PREC_MIXED, EXPORTS, HPSError,
+                  LIB_PATH, Solver, Tree, lib)
+
+__all__ = ["Tree", "Solver", "HPSError", "lib", "LIB_PATH", "EXPORTS",
+           "HPS_PREC_FP64", "HPS_PREC_MIXED", "HPS_PREC_FP32"]

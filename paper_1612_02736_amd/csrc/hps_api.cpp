@@ -1,0 +1,1232 @@
+// C ABI of the HPS solver: trees, build (Algorithm 1), solve (Algorithm 2),
+// adjoint sweeps and mixed-precision iterative refinement.
+//
+// The host planner turns the tree into fixed "programs": lists of kernel
+// launches over descriptor arrays that are uploaded once per handle.  A build
+// or solve is then a replay of its program on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hps.h"
+#include "handle.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "solve_ext.hpp"
+#include "spectral.hpp"
+#include "types.hpp"
+
+using namespace hps;
+
+namespace {
+
+
+// Host-side descriptor lists of one program, later uploaded.
+struct GemmList {
+  std::vector<GemmDesc> d;
+  std::vector<int64_t> t0;
+  int64_t tiles = 0;
+  void add(const GemmDesc &g0) {
+    GemmDesc g = g0;
+    g.tn = (g.N + 63) / 64;
+    const int64_t tm = (g.M + 63) / 64;
+    if (g.M <= 0 || g.N <= 0) return;
+    g.tile0 = tiles;
+    t0.push_back(tiles);
+    tiles += tm * g.tn;
+    d.push_back(g);
+  }
+};
+
+Ref ref(int32_t buf, int64_t off, int32_t ld) { return Ref{buf, ld, off}; }
+Ref noref() { return Ref{-1, 0, 0}; }
+VRef vref(int32_t buf, int64_t off, int64_t map, int64_t stride) {
+  return VRef{buf, 0, off, map, stride};
+}
+VRef novref() { return VRef{-1, 0, 0, -1, 0}; }
+
+}  // namespace
+
+extern "C" {
+
+const char *hps_last_error(void) { return hps::g_err.c_str(); }
+
+int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx, int ny,
+                     int n_problems, hps_tree **out) {
+  if (!out) return fail(HPS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nx <= 0 || ny <= 0 || n_problems <= 0 || !(x1 > x0) || !(y1 > y0))
+    return fail(HPS_EINVAL, "empty rectangle or non-positive leaf count");
+  hps_tree *t = new (std::nothrow) hps_tree;
+  if (!t) return fail(HPS_ENOMEM, "host allocation");
+  for (int k = 0; k < n_problems; ++k) {
+    Problem P;
+    P.X0 = x0; P.X1 = x1; P.Y0 = y0; P.Y1 = y1; P.nx = nx; P.ny = ny;
+    for (int i = 0; i < nx; ++i)
+      for (int j = 0; j < ny; ++j) P.leaves.insert({i * kUnit, j * kUnit, kUnit, kUnit, 0});
+    t->t.probs.push_back(std::move(P));
+  }
+  *out = t;
+  return HPS_OK;
+}
+
+int hps_tree_refine_point(hps_tree *tree, int problem, double px, double py, int n_ref,
+                          double t) {
+  if (!tree || n_ref < 0 || !(t >= 0.0)) return fail(HPS_EINVAL, "bad refinement arguments");
+  if (n_ref > 20) return fail(HPS_EINVAL, "n_ref > 20");
+  std::string e = refine_point(tree->t, problem, px, py, n_ref, t);
+  if (!e.empty()) return fail(HPS_ETREE, e);
+  return HPS_OK;
+}
+
+static int plan_tree(const TreeDesc &t, Plan &pl, int q) {
+  std::string e = build_tree_boxes(t, pl);
+  if (!e.empty()) return fail(HPS_ETREE, e);
+  if (q > 0) {
+    e = plan_gauss(t, pl, q);
+    if (!e.empty()) return fail(HPS_ETREE, e);
+  }
+  return HPS_OK;
+}
+
+int hps_tree_info(const hps_tree *tree, hps_tree_info_t *info) {
+  if (!tree || !info) return fail(HPS_EINVAL, "NULL argument");
+  Plan pl;
+  int rc = plan_tree(tree->t, pl, 0);
+  if (rc) return rc;
+  info->n_problems = (int)tree->t.probs.size();
+  info->n_leaves = (int)pl.leaves.size();
+  info->n_boxes = (int)pl.boxes.size();
+  info->n_levels = pl.max_height;
+  int md = 0;
+  for (auto &P : tree->t.probs)
+    for (auto &L : P.leaves) md = std::max(md, L.depth);
+  info->max_depth = md;
+  return HPS_OK;
+}
+
+int hps_tree_counts(const hps_tree *tree, int q, int64_t *n_gauss, int64_t *n_bdry) {
+  if (!tree || q < 1) return fail(HPS_EINVAL, "bad arguments");
+  Plan pl;
+  int rc = plan_tree(tree->t, pl, q);
+  if (rc) return rc;
+  if (n_gauss) *n_gauss = pl.n_gauss;
+  if (n_bdry) *n_bdry = (int64_t)pl.bdry.size();
+  return HPS_OK;
+}
+
+int hps_leaf_cheb_nodes(const hps_tree *tree, int p, double *xy) {
+  if (!tree || !xy || p < 2) return fail(HPS_EINVAL, "bad arguments");
+  Plan pl;
+  int rc = plan_tree(tree->t, pl, 0);
+  if (rc) return rc;
+  std::vector<double> xc = cheb_points(p);
+  size_t o = 0;
+  for (int li : pl.leaves) {
+    double x0, x1, y0, y1;
+    leaf_phys(tree->t, pl.boxes[li], x0, x1, y0, y1);
+    for (int iy = 0; iy < p; ++iy)
+      for (int ix = 0; ix < p; ++ix) {
+        xy[o++] = x0 + (x1 - x0) * (xc[ix] + 1.0) * 0.5;
+        xy[o++] = y0 + (y1 - y0) * (xc[iy] + 1.0) * 0.5;
+      }
+  }
+  return HPS_OK;
+}
+
+int hps_leaf_boxes(const hps_tree *tree, double *boxes) {
+  if (!tree || !boxes) return fail(HPS_EINVAL, "bad arguments");
+  Plan pl;
+  int rc = plan_tree(tree->t, pl, 0);
+  if (rc) return rc;
+  size_t o = 0;
+  for (int li : pl.leaves) {
+    double x0, x1, y0, y1;
+    leaf_phys(tree->t, pl.boxes[li], x0, x1, y0, y1);
+    boxes[o++] = x0; boxes[o++] = x1; boxes[o++] = y0; boxes[o++] = y1;
+  }
+  return HPS_OK;
+}
+
+int hps_bdry_gauss_nodes(const hps_tree *tree, int q, double *xy) {
+  if (!tree || !xy || q < 1) return fail(HPS_EINVAL, "bad arguments");
+  Plan pl;
+  int rc = plan_tree(tree->t, pl, q);
+  if (rc) return rc;
+  for (size_t i = 0; i < pl.bdry.size(); ++i) {
+    xy[2 * i] = pl.node_xy[2 * pl.bdry[i]];
+    xy[2 * i + 1] = pl.node_xy[2 * pl.bdry[i] + 1];
+  }
+  return HPS_OK;
+}
+
+int hps_gauss_nodes(const hps_tree *tree, int q, double *xy) {
+  if (!tree || !xy || q < 1) return fail(HPS_EINVAL, "bad arguments");
+  Plan pl;
+  int rc = plan_tree(tree->t, pl, q);
+  if (rc) return rc;
+  std::memcpy(xy, pl.node_xy.data(), pl.node_xy.size() * sizeof(double));
+  return HPS_OK;
+}
+
+void hps_tree_free(hps_tree *tree) { delete tree; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// planning of the device layout and the programs
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Layout {
+  // per box offsets (ws unless noted)
+  std::vector<int64_t> T, X, S, LD, H, Pup, Pdn, Pups;   // -1 if absent
+  std::vector<int64_t> Tn_scr, Tmp_scr, Aie_scr, B_scr, W_scr, ipiv;
+  std::vector<int64_t> h, w, hn;                          // vec offsets
+  std::vector<int64_t> map_fin, map_nat, map_gi, map_pi, map_slave;  // imap offsets
+  std::vector<int64_t> L_role;                 // ws, per role (5)
+  std::vector<int64_t> Dci, T0;                // ws, per (class*5 + role)
+  int64_t ws = 0, scr = 0, vec = 0, imap = 0, ipiv_n = 0, solve_ws = 0;
+};
+
+// Reference matrices of one leaf class/role, column-major where stored.
+struct LeafRef {
+  std::vector<double> Dh, Dh2;     // p x p row-major
+  std::vector<double> Lnat;        // me x 4q, column-major
+  std::vector<int> ice, ici;       // exterior / interior grid indices
+};
+
+LeafRef leaf_reference(int p, int q) {
+  LeafRef R;
+  std::vector<double> xc = cheb_points(p), xg = legendre_roots(q);
+  R.Dh = diff_matrix(xc);
+  R.Dh2.assign(size_t(p) * p, 0.0);
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < p; ++k) s += R.Dh[i * p + k] * R.Dh[k * p + j];
+      R.Dh2[i * p + j] = s;
+    }
+  for (int g = 0; g < p * p; ++g) {
+    int iy = g / p, ix = g % p;
+    bool in = iy > 0 && iy < p - 1 && ix > 0 && ix < p - 1;
+    (in ? R.ici : R.ice).push_back(g);
+  }
+  std::vector<double> G2C = interp_matrix(xg, xc);   // p x q row-major
+  const int me = (int)R.ice.size();
+  R.Lnat.assign(size_t(me) * 4 * q, 0.0);
+  auto put = [&](int r, int side, int t, double w) {
+    for (int k = 0; k < q; ++k) R.Lnat[r + size_t(me) * (side * q + k)] += w * G2C[t * q + k];
+  };
+  for (int r = 0; r < me; ++r) {
+    int g = R.ice[r], iy = g / p, ix = g % p;
+    bool cx = ix == 0 || ix == p - 1, cy = iy == 0 || iy == p - 1;
+    if (cx && cy) {
+      put(r, iy == 0 ? 0 : 2, ix, 0.5);
+      put(r, ix == 0 ? 3 : 1, iy, 0.5);
+    } else if (iy == 0) put(r, 0, ix, 1.0);
+    else if (iy == p - 1) put(r, 2, ix, 1.0);
+    else if (ix == 0) put(r, 3, iy, 1.0);
+    else put(r, 1, iy, 1.0);
+  }
+  return R;
+}
+
+// side order of a leaf with role r: the three kept sides, then the shared one
+void role_sides(int role, int so[4]) {
+  int k = 0;
+  for (int s = 0; s < 4; ++s)
+    if (s != role) so[k++] = s;
+  if (role < 4) so[3] = role;
+}
+
+// D_ge,c of a leaf with sides in role order (4q x p^2, row-major)
+std::vector<double> leaf_dge(int p, int q, double hx, double hy, int role) {
+  std::vector<double> xc = cheb_points(p), xg = legendre_roots(q);
+  std::vector<double> D = diff_matrix(xc), Lloc = interp_matrix(xc, xg);  // q x p
+  const double sx = 2.0 / hx, sy = 2.0 / hy;
+  std::vector<double> nat(size_t(4) * q * p * p, 0.0);
+  for (int k = 0; k < q; ++k)
+    for (int jy = 0; jy < p; ++jy)
+      for (int jx = 0; jx < p; ++jx) {
+        const int c = jy * p + jx;
+        nat[size_t(0 * q + k) * p * p + c] = Lloc[k * p + jx] * sy * D[0 * p + jy];
+        nat[size_t(1 * q + k) * p * p + c] = Lloc[k * p + jy] * sx * D[(p - 1) * p + jx];
+        nat[size_t(2 * q + k) * p * p + c] = Lloc[k * p + jx] * sy * D[(p - 1) * p + jy];
+        nat[size_t(3 * q + k) * p * p + c] = Lloc[k * p + jy] * sx * D[0 * p + jx];
+      }
+  int so[4];
+  role_sides(role, so);
+  std::vector<double> out(nat.size());
+  for (int j = 0; j < 4; ++j)
+    std::memcpy(&out[size_t(j) * q * p * p], &nat[size_t(so[j]) * q * p * p],
+                sizeof(double) * q * p * p);
+  return out;
+}
+
+void gemm_step(GemmList &gl, GemmList &tmp, std::vector<Step> &prog) {
+  if (tmp.d.empty()) return;
+  Step s{S_GEMM};
+  s.d0 = (int64_t)gl.d.size();
+  s.nd = (int64_t)tmp.d.size();
+  s.ntiles = tmp.tiles;
+  for (auto &g : tmp.d) gl.d.push_back(g);
+  for (auto t : tmp.t0) gl.t0.push_back(t);
+  prog.push_back(s);
+}
+
+// Launch steps that invert the interface blocks of one level: the
+// register-resident kernel per size class, the blocked path above it.
+void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeInvDesc> &minv,
+                        GemmList &gl, std::vector<Step> &prog) {
+  std::vector<MergeInvDesc> cls_d[4], big;
+  int bigmax = 0;
+  for (const MergeInvDesc &d : lev) {
+    int cls = gj_merge_class(d.m);
+    if (cls >= 0) cls_d[cls].push_back(d);
+    else { big.push_back(d); bigmax = std::max(bigmax, d.m); }
+  }
+  for (int c = 0; c < 4; ++c) {
+    if (cls_d[c].empty()) continue;
+    Step s{S_GJ_MERGE};
+    s.cls = c;
+    s.d0 = (int64_t)minv.size();
+    s.nd = (int64_t)cls_d[c].size();
+    minv.insert(minv.end(), cls_d[c].begin(), cls_d[c].end());
+    prog.push_back(s);
+  }
+  if (big.empty()) return;
+  const int64_t d0 = (int64_t)minv.size();
+  minv.insert(minv.end(), big.begin(), big.end());
+  Step z{S_ZDIFF};
+  z.d0 = d0; z.nd = (int64_t)big.size(); z.maxm = bigmax;
+  prog.push_back(z);
+  for (int kb = 0; kb < bigmax; kb += kPanelNB) {
+    Step s{S_PANEL};
+    s.d0 = d0; s.nd = (int64_t)big.size(); s.kb = kb; s.maxm = bigmax;
+    prog.push_back(s);
+    GemmList up;
+    for (const MergeInvDesc &d : big) {
+      const int m = d.m;
+      if (kb >= m) continue;
+      const int nbv = std::min(kPanelNB, m - kb), ke = kb + nbv;
+      const int rows[3][2] = {{0, kb}, {kb, ke}, {ke, m}};
+      const int cols[2][2] = {{0, kb}, {ke, m}};
+      for (int ri = 0; ri < 3; ++ri)
+        for (int ci = 0; ci < 2; ++ci) {
+          const int r0 = rows[ri][0], r1 = rows[ri][1], c0 = cols[ci][0], c1 = cols[ci][1];
+          if (r1 <= r0 || c1 <= c0) continue;
+          GemmDesc g{};
+          g.M = r1 - r0; g.N = c1 - c0; g.K = nbv;
+          g.A = ref(BUF_WS, d.X + r0 + int64_t(kb) * m, m);
+          g.B = ref(BUF_SCR, d.W + int64_t(c0) * kPanelNB, kPanelNB);
+          g.C = ref(BUF_WS, d.X + r0 + int64_t(c0) * m, m);
+          g.D = (ri == 1) ? noref() : ref(BUF_WS, d.X + r0 + int64_t(c0) * m, m);
+          g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = (ri == 1) ? 0.0 : 1.0;
+          up.add(g);
+        }
+    }
+    gemm_step(gl, up, prog);
+  }
+  Step cp{S_COLPERM};
+  cp.d0 = d0; cp.nd = (int64_t)big.size(); cp.maxm = bigmax;
+  prog.push_back(cp);
+}
+
+}  // namespace
+
+// Builds layout, uploads reference matrices and maps, generates programs.
+static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
+                       std::vector<std::pair<int64_t, std::vector<double>>> &ws_blocks,
+                       std::vector<int32_t> &imap, GemmList &gl, std::vector<LeafDesc> &leafd,
+                       std::vector<MergeInvDesc> &minv, std::vector<ApplyDesc> &appl,
+                       std::vector<int64_t> &appl_t0, std::vector<int32_t> &finlist) {
+  Plan &pl = H->pl;
+  const int p = H->p, q = H->q, mi = H->mi, me = H->me, g4 = H->g4;
+  const int nb = (int)pl.boxes.size();
+  const int nleaf = H->nleaf;
+  Lo.T.assign(nb, -1); Lo.X.assign(nb, -1); Lo.S.assign(nb, -1); Lo.LD.assign(nb, -1);
+  Lo.H.assign(nb, -1); Lo.Pup.assign(nb, -1); Lo.Pdn.assign(nb, -1); Lo.Pups.assign(nb, -1);
+  Lo.Tn_scr.assign(nb, -1); Lo.Tmp_scr.assign(nb, -1); Lo.Aie_scr.assign(nb, -1);
+  Lo.B_scr.assign(nb, -1); Lo.W_scr.assign(nb, -1); Lo.ipiv.assign(nb, -1);
+  Lo.h.assign(nb, -1); Lo.w.assign(nb, -1); Lo.hn.assign(nb, -1);
+  Lo.map_fin.assign(nb, -1); Lo.map_nat.assign(nb, -1); Lo.map_gi.assign(nb, -1);
+  Lo.map_pi.assign(nb, -1); Lo.map_slave.assign(nb, -1);
+  auto ws_take = [&](int64_t n) { int64_t o = Lo.ws; Lo.ws += (n + 31) / 32 * 32; return o; };
+  auto scr_take = [&](int64_t n) { int64_t o = Lo.scr; Lo.scr += (n + 31) / 32 * 32; return o; };
+  auto vec_take = [&](int64_t n) { int64_t o = Lo.vec; Lo.vec += n; return o; };
+  auto imap_put = [&](const std::vector<int32_t> &v) {
+    int64_t o = (int64_t)imap.size();
+    imap.insert(imap.end(), v.begin(), v.end());
+    return o;
+  };
+  auto imap_put64 = [&](const std::vector<int64_t> &v) {
+    std::vector<int32_t> w(v.begin(), v.end());
+    return imap_put(w);
+  };
+  // --- solve-stage operators first (they are the FP32-copied prefix) ---
+  Lo.vec = pl.n_gauss;   // global u at the start of each RHS block
+  H->ug_off = 0;
+  for (int li : pl.leaves) {
+    Lo.LD[li] = ws_take(int64_t(mi) * (g4 + mi));
+    Lo.H[li] = ws_take(int64_t(g4) * mi);
+  }
+  for (int b = 0; b < nb; ++b) {
+    const Box &B = pl.boxes[b];
+    const int ef = (int)B.fin.size();
+    if (B.parent >= 0) Lo.T[b] = ws_take(int64_t(ef) * ef);
+    if (!B.leaf) {
+      const int m = (int)B.gi.size(), en = (int)B.nat.size();
+      Lo.X[b] = ws_take(int64_t(m) * m);
+      Lo.S[b] = ws_take(int64_t(m) * en);
+      if (B.coarsened) {
+        Lo.Pdn[b] = ws_take(int64_t(ef) * en);
+        Lo.Pups[b] = ws_take(int64_t(B.slave_rows.size()) * ef);
+        Lo.Pup[b] = ws_take(int64_t(en) * ef);
+      }
+    }
+  }
+  // reference matrices per role / size class
+  LeafRef R = leaf_reference(p, q);
+  Lo.L_role.assign(5, -1);
+  for (int r = 0; r < 5; ++r) {
+    int so[4];
+    role_sides(r, so);
+    std::vector<double> L(size_t(me) * g4);
+    for (int j = 0; j < 4; ++j)
+      std::memcpy(&L[size_t(me) * j * q], &R.Lnat[size_t(me) * so[j] * q],
+                  sizeof(double) * me * q);
+    Lo.L_role[r] = ws_take(int64_t(me) * g4);
+    ws_blocks.push_back({Lo.L_role[r], L});
+  }
+  Lo.solve_ws = Lo.ws;
+  const int ncls = (int)pl.size_class.size();
+  Lo.Dci.assign(size_t(ncls) * 5, -1);
+  Lo.T0.assign(size_t(ncls) * 5, -1);
+  std::vector<char> need(size_t(ncls) * 5, 0);
+  for (int i = 0; i < nleaf; ++i) need[size_t(pl.leaf_class[i]) * 5 + pl.boxes[pl.leaves[i]].role] = 1;
+  for (int c = 0; c < ncls; ++c)
+    for (int r = 0; r < 5; ++r) {
+      if (!need[size_t(c) * 5 + r]) continue;
+      std::vector<double> Dg = leaf_dge(p, q, pl.size_class[c].first, pl.size_class[c].second, r);
+      std::vector<double> Dci(size_t(g4) * mi), T0(size_t(g4) * g4, 0.0);
+      for (int a = 0; a < mi; ++a)
+        for (int k = 0; k < g4; ++k) Dci[k + size_t(g4) * a] = Dg[size_t(k) * p * p + R.ici[a]];
+      // T0 = D_ge,ce L (role order)
+      int so[4];
+      role_sides(r, so);
+      for (int k = 0; k < g4; ++k)
+        for (int j = 0; j < g4; ++j) {
+          const int js = so[j / q] * q + j % q;   // natural column of L
+          double s = 0.0;
+          for (int e = 0; e < me; ++e)
+            s += Dg[size_t(k) * p * p + R.ice[e]] * R.Lnat[e + size_t(me) * js];
+          T0[k + size_t(g4) * j] = s;
+        }
+      Lo.Dci[size_t(c) * 5 + r] = ws_take(int64_t(g4) * mi);
+      Lo.T0[size_t(c) * 5 + r] = ws_take(int64_t(g4) * g4);
+      ws_blocks.push_back({Lo.Dci[size_t(c) * 5 + r], Dci});
+      ws_blocks.push_back({Lo.T0[size_t(c) * 5 + r], T0});
+    }
+  // P_up / P_down of coarsened boxes
+  for (int b = 0; b < nb; ++b) {
+    const Box &B = pl.boxes[b];
+    if (!B.coarsened) continue;
+    const int ef = (int)B.fin.size(), en = (int)B.nat.size();
+    ws_blocks.push_back({Lo.Pup[b], B.Pup});
+    ws_blocks.push_back({Lo.Pdn[b], B.Pdn});
+    std::vector<double> Ps(size_t(B.slave_rows.size()) * ef);
+    const int ns = (int)B.slave_rows.size();
+    for (int j = 0; j < ef; ++j)
+      for (int a = 0; a < ns; ++a) Ps[a + size_t(ns) * j] = B.Pup[B.slave_rows[a] + size_t(en) * j];
+    ws_blocks.push_back({Lo.Pups[b], Ps});
+  }
+  // leaf temporaries and T
+  for (int i = 0; i < nleaf; ++i) {
+    const int li = pl.leaves[i];
+    if (Lo.T[li] < 0) Lo.T[li] = ws_take(int64_t(g4) * g4);   // single-leaf root
+    Lo.Aie_scr[li] = scr_take(int64_t(mi) * me);
+    Lo.B_scr[li] = scr_take(int64_t(mi) * g4);
+  }
+  for (int b = 0; b < nb; ++b) {
+    const Box &B = pl.boxes[b];
+    if (B.leaf) continue;
+    const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
+    if (gj_merge_class(m) < 0) {
+      Lo.W_scr[b] = scr_take(std::max<int64_t>(int64_t(kPanelNB) * m, int64_t(m) * m));
+      Lo.ipiv[b] = Lo.ipiv_n;
+      Lo.ipiv_n += m;
+    }
+    if (B.coarsened && B.parent >= 0) {
+      Lo.Tn_scr[b] = scr_take(int64_t(en) * en);
+      Lo.Tmp_scr[b] = scr_take(int64_t(en) * ef);
+    }
+  }
+  // --- vectors (per RHS) ---
+  for (int b = 0; b < nb; ++b) {
+    const Box &B = pl.boxes[b];
+    Lo.h[b] = vec_take((int64_t)B.fin.size());
+    if (!B.leaf) {
+      Lo.w[b] = vec_take((int64_t)B.gi.size());
+      if (B.coarsened) Lo.hn[b] = vec_take((int64_t)B.nat.size());
+    }
+  }
+  // --- integer maps ---
+  for (int b = 0; b < nb; ++b) {
+    const Box &B = pl.boxes[b];
+    Lo.map_fin[b] = imap_put64(B.fin);
+    if (!B.leaf) {
+      Lo.map_nat[b] = imap_put64(B.nat);
+      Lo.map_gi[b] = imap_put64(B.gi);
+      if (!B.coarsened) {
+        std::vector<int32_t> pi(B.pi.begin(), B.pi.end());
+        Lo.map_pi[b] = imap_put(pi);
+      } else {
+        std::vector<int32_t> sl;
+        for (int a : B.slave_rows) sl.push_back((int32_t)B.nat[a]);
+        Lo.map_slave[b] = imap_put(sl);
+      }
+    }
+  }
+  {
+    std::vector<int32_t> v(R.ice.begin(), R.ice.end());
+    H->ice_map = imap_put(v);
+    std::vector<int32_t> w(R.ici.begin(), R.ici.end());
+    H->ici_map = imap_put(w);
+    H->map_bdry = imap_put64(pl.bdry);
+    H->n_bdry = (int64_t)pl.bdry.size();
+  }
+  // aux: Dh, Dh2
+  ws_init.clear();
+  ws_init.insert(ws_init.end(), R.Dh.begin(), R.Dh.end());
+  ws_init.insert(ws_init.end(), R.Dh2.begin(), R.Dh2.end());
+  H->Dh_off = 0;
+  H->Dh2_off = int64_t(p) * p;
+
+  // ======================= build program =======================
+  auto &prog = H->build_prog;
+  prog.clear();
+  // leaves: Gauss-Jordan
+  for (int i = 0; i < nleaf; ++i) {
+    const int li = pl.leaves[i];
+    const auto &sc = pl.size_class[pl.leaf_class[i]];
+    LeafDesc d{};
+    d.coef = int64_t(i) * 6 * p * p;
+    d.F = Lo.LD[li] + int64_t(g4) * mi;
+    d.Aie = Lo.Aie_scr[li];
+    d.sx = 2.0 / sc.first;
+    d.sy = 2.0 / sc.second;
+    d.info = i;
+    leafd.push_back(d);
+  }
+  {
+    Step s{S_GJ_LEAF};
+    s.d0 = 0;
+    s.nd = nleaf;
+    prog.push_back(s);
+  }
+  {
+    GemmList a, b2, c;
+    for (int i = 0; i < nleaf; ++i) {
+      const int li = pl.leaves[i];
+      const int role = pl.boxes[li].role, cls = pl.leaf_class[i];
+      const int64_t F = Lo.LD[li] + int64_t(g4) * mi;
+      const int64_t Dci = Lo.Dci[size_t(cls) * 5 + role], T0 = Lo.T0[size_t(cls) * 5 + role];
+      GemmDesc g{};
+      // B = A_ci,ce L
+      g = GemmDesc{};
+      g.M = mi; g.N = g4; g.K = me;
+      g.A = ref(BUF_SCR, Lo.Aie_scr[li], mi); g.B = ref(BUF_WS, Lo.L_role[role], me);
+      g.C = ref(BUF_SCR, Lo.B_scr[li], mi); g.D = noref();
+      g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
+      a.add(g);
+      // H = D_ge,ci F
+      g = GemmDesc{};
+      g.M = g4; g.N = mi; g.K = mi;
+      g.A = ref(BUF_WS, Dci, g4); g.B = ref(BUF_WS, F, mi);
+      g.C = ref(BUF_WS, Lo.H[li], g4); g.D = noref();
+      g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
+      a.add(g);
+      // S_ci = -F B
+      g = GemmDesc{};
+      g.M = mi; g.N = g4; g.K = mi;
+      g.A = ref(BUF_WS, F, mi); g.B = ref(BUF_SCR, Lo.B_scr[li], mi);
+      g.C = ref(BUF_WS, Lo.LD[li], mi); g.D = noref();
+      g.crow = g.ccol = -1; g.alpha = -1.0; g.beta = 0.0;
+      b2.add(g);
+      // T = T0 + D_ge,ci S_ci
+      g = GemmDesc{};
+      g.M = g4; g.N = g4; g.K = mi;
+      g.A = ref(BUF_WS, Dci, g4); g.B = ref(BUF_WS, Lo.LD[li], mi);
+      g.C = ref(BUF_WS, Lo.T[li], g4); g.D = ref(BUF_WS, T0, g4);
+      g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 1.0;
+      c.add(g);
+    }
+    gemm_step(gl, a, prog);
+    gemm_step(gl, b2, prog);
+    gemm_step(gl, c, prog);
+  }
+  // merges, level by level
+  int info_slot = nleaf;
+  for (int h = 1; h <= pl.max_height; ++h) {
+    std::vector<int> lev;
+    for (int b = 0; b < nb; ++b)
+      if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
+    if (lev.empty()) continue;
+    std::vector<MergeInvDesc> levd;
+    for (int b : lev) {
+      const Box &B = pl.boxes[b];
+      const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+      const int m = (int)B.gi.size();
+      const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+      const int n1 = ea - m, n2 = eb - m;
+      MergeInvDesc d{};
+      d.Ta = Lo.T[B.alpha] + n1 + int64_t(n1) * ea;
+      d.Tb = Lo.T[B.beta] + n2 + int64_t(n2) * eb;
+      d.lda = ea; d.ldb = eb; d.m = m; d.info = info_slot++;
+      d.X = Lo.X[b];
+      d.W = Lo.W_scr[b];
+      d.ipiv = Lo.ipiv[b];
+      levd.push_back(d);
+    }
+    emit_inverse_steps(levd, minv, gl, prog);
+    // S = X [-T31a | T32b]
+    GemmList sg, tg, c1, c2;
+    for (int b : lev) {
+      const Box &B = pl.boxes[b];
+      const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+      const int m = (int)B.gi.size();
+      const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+      const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
+      GemmDesc g{};
+      g.M = m; g.N = n1; g.K = m;
+      g.A = ref(BUF_WS, Lo.X[b], m); g.B = ref(BUF_WS, Lo.T[B.alpha] + n1, ea);
+      g.C = ref(BUF_WS, Lo.S[b], m); g.D = noref(); g.crow = g.ccol = -1;
+      g.alpha = -1.0; g.beta = 0.0;
+      sg.add(g);
+      g = GemmDesc{};
+      g.M = m; g.N = n2; g.K = m;
+      g.A = ref(BUF_WS, Lo.X[b], m); g.B = ref(BUF_WS, Lo.T[B.beta] + n2, eb);
+      g.C = ref(BUF_WS, Lo.S[b] + int64_t(n1) * m, m); g.D = noref(); g.crow = g.ccol = -1;
+      g.alpha = 1.0; g.beta = 0.0;
+      sg.add(g);
+      if (B.parent < 0) continue;   // the root's T is never used
+      // T = blkdiag(T11a, T22b) + [T13a; T23b] S, written in final order
+      Ref Cout;
+      int64_t pr = -1;
+      if (B.coarsened) Cout = ref(BUF_SCR, Lo.Tn_scr[b], en);
+      else { Cout = ref(BUF_WS, Lo.T[b], ef); pr = Lo.map_pi[b]; }
+      const int64_t Ta = Lo.T[B.alpha], Tb = Lo.T[B.beta];
+      for (int bi = 0; bi < 2; ++bi)
+        for (int bj = 0; bj < 2; ++bj) {
+          GemmDesc t{};
+          t.M = bi == 0 ? n1 : n2;
+          t.N = bj == 0 ? n1 : n2;
+          t.K = m;
+          t.A = bi == 0 ? ref(BUF_WS, Ta + int64_t(n1) * ea, ea) : ref(BUF_WS, Tb + int64_t(n2) * eb, eb);
+          t.B = ref(BUF_WS, Lo.S[b] + (bj == 0 ? 0 : int64_t(n1) * m), m);
+          if (bi == bj) t.D = bi == 0 ? ref(BUF_WS, Ta, ea) : ref(BUF_WS, Tb, eb);
+          else t.D = noref();
+          t.alpha = 1.0; t.beta = (bi == bj) ? 1.0 : 0.0;
+          const int r0 = bi == 0 ? 0 : n1, c0 = bj == 0 ? 0 : n1;
+          if (pr >= 0) {
+            t.C = Cout; t.crow = pr + r0; t.ccol = pr + c0;
+          } else {
+            t.C = ref(Cout.buf, Cout.off + r0 + int64_t(c0) * en, en);
+            t.crow = t.ccol = -1;
+          }
+          tg.add(t);
+        }
+      if (B.coarsened) {
+        GemmDesc u{};
+        u.M = en; u.N = ef; u.K = en;
+        u.A = ref(BUF_SCR, Lo.Tn_scr[b], en); u.B = ref(BUF_WS, Lo.Pup[b], en);
+        u.C = ref(BUF_SCR, Lo.Tmp_scr[b], en); u.D = noref(); u.crow = u.ccol = -1;
+        u.alpha = 1.0; u.beta = 0.0;
+        c1.add(u);
+        GemmDesc v{};
+        v.M = ef; v.N = ef; v.K = en;
+        v.A = ref(BUF_WS, Lo.Pdn[b], ef); v.B = ref(BUF_SCR, Lo.Tmp_scr[b], en);
+        v.C = ref(BUF_WS, Lo.T[b], ef); v.D = noref(); v.crow = v.ccol = -1;
+        v.alpha = 1.0; v.beta = 0.0;
+        c2.add(v);
+      }
+    }
+    gemm_step(gl, sg, prog);
+    gemm_step(gl, tg, prog);
+    gemm_step(gl, c1, prog);
+    gemm_step(gl, c2, prog);
+  }
+  H->n_info = info_slot;
+
+  // ======================= solve programs =======================
+  const int64_t VS = 0;  // stride placeholder; patched per call through vec_per_rhs
+  (void)VS;
+  H->vec_per_rhs = Lo.vec;
+  const int64_t vs = Lo.vec;
+  const int64_t gstride = int64_t(nleaf) * mi, ustride = int64_t(nleaf) * p * p;
+  int64_t part_off = 0;
+  auto apply_step = [&](std::vector<ApplyDesc> &tmp, std::vector<Step> &prg) {
+    if (tmp.empty()) return;
+    Step s{S_APPLY};
+    s.d0 = (int64_t)appl.size();
+    s.nd = (int64_t)tmp.size();
+    int64_t tiles = 0;
+    s.fin0 = (int64_t)finlist.size();
+    for (auto &a : tmp) {
+      const int K = a.K1 + (a.mode == 0 ? a.K2 : 0);
+      a.rb = (a.M + 63) / 64;
+      a.ksl = std::max(1, std::min(64, (K + 511) / 512));
+      if (int64_t(a.rb) * a.ksl < 4 && K >= 256) a.ksl = std::max(a.ksl, std::min(8, K / 128));
+      a.tile0 = tiles;
+      appl_t0.push_back(tiles);
+      tiles += int64_t(a.rb) * a.ksl;
+      if (a.ksl > 1) {
+        a.part = part_off;
+        part_off += int64_t(a.ksl) * a.M;
+        finlist.push_back((int32_t)appl.size());
+        s.fin_maxm = std::max<int64_t>(s.fin_maxm, a.M);
+      }
+      appl.push_back(a);
+    }
+    s.ntiles = tiles;
+    s.nfin = (int64_t)finlist.size() - s.fin0;
+    prg.push_back(s);
+    tmp.clear();
+  };
+  auto ad = [&](int M, int K1, int K2, int mode, int64_t aoff, int lda) {
+    ApplyDesc a{};
+    a.M = M; a.K1 = K1; a.K2 = K2; a.mode = mode;
+    a.abuf = BUF_WS; a.aoff = aoff; a.lda = lda;
+    a.B1 = novref(); a.B2 = novref(); a.B3 = novref(); a.C = novref(); a.D = novref();
+    a.alpha = 1.0; a.beta = 0.0;
+    return a;
+  };
+  // up pass
+  {
+    auto &up = H->up_prog;
+    up.clear();
+    std::vector<ApplyDesc> tmp;
+    for (int i = 0; i < nleaf; ++i) {
+      const int li = pl.leaves[i];
+      ApplyDesc a = ad(g4, mi, 0, 0, Lo.H[li], g4);
+      a.B1 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
+      a.C = vref(BUF_VEC, Lo.h[li], -1, vs);
+      tmp.push_back(a);
+    }
+    apply_step(tmp, up);
+    for (int h = 1; h <= pl.max_height; ++h) {
+      std::vector<int> lev;
+      for (int b = 0; b < nb; ++b)
+        if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
+      if (lev.empty()) continue;
+      std::vector<ApplyDesc> wst, hst, cst;
+      for (int b : lev) {
+        const Box &B = pl.boxes[b];
+        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+        const int m = (int)B.gi.size();
+        const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+        const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
+        ApplyDesc a = ad(m, m, 0, 1, Lo.X[b], m);
+        a.B1 = vref(BUF_VEC, Lo.h[B.beta] + n2, -1, vs);
+        a.B2 = vref(BUF_VEC, Lo.h[B.alpha] + n1, -1, vs);
+        a.B3 = vref(BUF_AUX, 0, Lo.map_gi[b], 0);   // flux-jump source; buf patched
+        a.B3.buf = -1;
+        a.C = vref(BUF_VEC, Lo.w[b], -1, vs);
+        wst.push_back(a);
+        if (B.parent < 0) continue;
+        for (int part = 0; part < 2; ++part) {
+          const int M = part == 0 ? n1 : n2;
+          if (M == 0) continue;
+          const int64_t Tsrc = part == 0 ? Lo.T[B.alpha] + int64_t(n1) * ea
+                                         : Lo.T[B.beta] + int64_t(n2) * eb;
+          ApplyDesc c = ad(M, m, 0, 0, Tsrc, part == 0 ? ea : eb);
+          c.B1 = vref(BUF_VEC, Lo.w[b], -1, vs);
+          c.D = vref(BUF_VEC, part == 0 ? Lo.h[B.alpha] : Lo.h[B.beta], -1, vs);
+          c.beta = 1.0;
+          if (B.coarsened) c.C = vref(BUF_VEC, Lo.hn[b] + (part == 0 ? 0 : n1), -1, vs);
+          else c.C = vref(BUF_VEC, Lo.h[b], Lo.map_pi[b] + (part == 0 ? 0 : n1), vs);
+          hst.push_back(c);
+        }
+        if (B.coarsened) {
+          ApplyDesc c = ad(ef, en, 0, 0, Lo.Pdn[b], ef);
+          c.B1 = vref(BUF_VEC, Lo.hn[b], -1, vs);
+          c.C = vref(BUF_VEC, Lo.h[b], -1, vs);
+          cst.push_back(c);
+        }
+      }
+      apply_step(wst, up);
+      apply_step(hst, up);
+      apply_step(cst, up);
+    }
+  }
+  // down pass
+  {
+    auto &dn = H->down_prog;
+    dn.clear();
+    std::vector<ApplyDesc> tmp;
+    for (int h = pl.max_height; h >= 1; --h) {
+      std::vector<int> lev;
+      for (int b = 0; b < nb; ++b)
+        if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
+      if (lev.empty()) continue;
+      std::vector<ApplyDesc> sl, ug;
+      for (int b : lev) {
+        const Box &B = pl.boxes[b];
+        const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
+        if (B.coarsened && !B.slave_rows.empty()) {
+          ApplyDesc a = ad((int)B.slave_rows.size(), ef, 0, 0, Lo.Pups[b], (int)B.slave_rows.size());
+          a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[b], vs);
+          a.C = vref(BUF_VEC, H->ug_off, Lo.map_slave[b], vs);
+          sl.push_back(a);
+        }
+        ApplyDesc a = ad(m, en, 0, 0, Lo.S[b], m);
+        a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_nat[b], vs);
+        a.D = vref(BUF_VEC, Lo.w[b], -1, vs);
+        a.beta = 1.0;
+        a.C = vref(BUF_VEC, H->ug_off, Lo.map_gi[b], vs);
+        ug.push_back(a);
+      }
+      apply_step(sl, dn);
+      apply_step(ug, dn);
+    }
+    for (int i = 0; i < nleaf; ++i) {
+      const int li = pl.leaves[i];
+      const int role = pl.boxes[li].role;
+      ApplyDesc a = ad(mi, g4, mi, 0, Lo.LD[li], mi);
+      a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], vs);
+      a.B2 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
+      a.C = vref(BUF_IN2, int64_t(i) * p * p, H->ici_map, ustride);
+      tmp.push_back(a);
+      ApplyDesc e = ad(me, g4, 0, 0, Lo.L_role[role], me);
+      e.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], vs);
+      e.C = vref(BUF_IN2, int64_t(i) * p * p, H->ice_map, ustride);
+      tmp.push_back(e);
+    }
+    apply_step(tmp, dn);
+  }
+  H->part_per_rhs = part_off;
+  H->off_T = Lo.T; H->off_X = Lo.X; H->off_S = Lo.S; H->off_LD = Lo.LD; H->off_H = Lo.H;
+  return HPS_OK;
+}
+
+static Bases make_bases(hps_handle *H) {
+  Bases b{};
+  b.d[BUF_WS] = H->ws.p;
+  b.d[BUF_SCR] = H->scr.p;
+  b.d[BUF_VEC] = H->vec.p;
+  b.d[BUF_W32] = H->ws32.p;
+  b.d[BUF_AUX] = H->aux.p;
+  b.imap = H->imap.p;
+  return b;
+}
+
+static hipEvent_t prof_event(hps_handle *H) {
+  if (H->prof_used == H->prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    H->prof_pool.push_back(e);
+  }
+  return H->prof_pool[H->prof_used++];
+}
+
+static int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, int prec,
+                    hipStream_t st) {
+  for (const Step &s : prog) {
+    hipError_t e = hipSuccess;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (H->prof_on) {
+      e0 = prof_event(H);
+      e1 = prof_event(H);
+      if (e0 && e1) (void)hipEventRecord(e0, st);
+    }
+    switch (s.kind) {
+      case S_GEMM:
+        e = launch_gemm(H->d_gemm.p + s.d0, H->d_gemm_t0.p + s.d0, (int)s.nd, s.ntiles, bs, st);
+        break;
+      case S_GJ_LEAF:
+        e = launch_gj_leaf(H->p, H->d_leaf.p + s.d0, (int)s.nd, bs, H->aux.p + H->Dh_off,
+                           H->aux.p + H->Dh2_off, H->imap.p + H->ice_map, H->me, H->info.p, st);
+        break;
+      case S_GJ_MERGE:
+        e = launch_gj_merge(s.cls, H->d_minv.p + s.d0, (int)s.nd, bs, H->info.p, st);
+        break;
+      case S_ZDIFF:
+        e = launch_zdiff(H->d_minv.p + s.d0, (int)s.nd, s.maxm, bs, st);
+        break;
+      case S_PANEL:
+        e = launch_gj_panel(H->d_minv.p + s.d0, (int)s.nd, s.kb, s.maxm, bs, H->ipiv.p,
+                            H->info.p, st);
+        break;
+      case S_COLPERM:
+        e = launch_gj_colperm(H->d_minv.p + s.d0, (int)s.nd, s.maxm, bs, H->ipiv.p, H->psrc.p,
+                              st);
+        break;
+      case S_APPLY:
+        e = launch_apply(prec, H->d_apply.p + s.d0, H->d_apply_t0.p + s.d0, (int)s.nd, s.ntiles,
+                         bs, nrhs, st);
+        if (e == hipSuccess && s.nfin > 0)
+          e = launch_apply_finalize(H->d_apply.p, H->d_finlist.p + s.fin0, (int)s.nfin,
+                                    s.fin_maxm, bs, nrhs, st);
+        break;
+      default:
+        break;
+    }
+    if (e != hipSuccess) return fail(HPS_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (H->prof_on && e0 && e1) {
+      (void)hipEventRecord(e1, st);
+      int kind = int(s.kind) * 16 + (s.kind == S_GJ_MERGE ? s.cls : 0);
+      if (s.kind == S_APPLY) kind += prec;
+      H->prof_ev.push_back({kind, {e0, e1}});
+    }
+  }
+  return HPS_OK;
+}
+
+extern "C" {
+
+size_t hps_build_workspace_size(const hps_tree *tree, int p, int q) {
+  if (!tree || p < 4) return 0;
+  if (q <= 0) q = p - 1;
+  hps_handle H;
+  H.tree = tree->t;
+  if (plan_tree(H.tree, H.pl, q)) return 0;
+  H.p = p; H.q = q; H.mi = (p - 2) * (p - 2); H.me = 4 * (p - 1); H.g4 = 4 * q;
+  H.nleaf = (int)H.pl.leaves.size();
+  Layout Lo;
+  std::vector<double> wi;
+  std::vector<std::pair<int64_t, std::vector<double>>> blocks;
+  std::vector<int32_t> imap;
+  GemmList gl;
+  std::vector<LeafDesc> ld;
+  std::vector<MergeInvDesc> mv;
+  std::vector<ApplyDesc> ap;
+  std::vector<int64_t> at0;
+  std::vector<int32_t> fl;
+  if (plan_handle(&H, Lo, wi, blocks, imap, gl, ld, mv, ap, at0, fl)) return 0;
+  return size_t(Lo.ws) * sizeof(double);
+}
+
+int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build_opts *opts,
+              hps_handle **out) {
+  if (!out) return fail(HPS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!tree || !coeffs) return fail(HPS_EINVAL, "NULL tree or coefficients");
+  int q = opts && opts->q > 0 ? opts->q : p - 1;
+  if (p < 4 || q < 2 || q >= p) return fail(HPS_EINVAL, "need p >= 4 and 2 <= q < p");
+  if (!gj_leaf_supported(p)) return fail(HPS_EINVAL, "p must be one of 6, 8, 10, 12, 16");
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  std::unique_ptr<hps_handle> H(new (std::nothrow) hps_handle);
+  if (!H) return fail(HPS_ENOMEM, "host allocation");
+  H->tree = tree->t;
+  int rc = plan_tree(H->tree, H->pl, q);
+  if (rc) return rc;
+  H->p = p; H->q = q; H->mi = (p - 2) * (p - 2); H->me = 4 * (p - 1); H->g4 = 4 * q;
+  H->nleaf = (int)H->pl.leaves.size();
+  for (const Box &b : H->pl.boxes)
+    if (!b.leaf && (int)b.gi.size() > 2048)
+      return fail(HPS_EINVAL, "interface longer than 2048 nodes");
+  Layout Lo;
+  std::vector<double> aux_init;
+  std::vector<std::pair<int64_t, std::vector<double>>> blocks;
+  std::vector<int32_t> imap;
+  GemmList gl;
+  std::vector<LeafDesc> leafd;
+  std::vector<MergeInvDesc> minv;
+  std::vector<ApplyDesc> appl;
+  std::vector<int64_t> appl_t0;
+  std::vector<int32_t> finlist;
+  rc = plan_handle(H.get(), Lo, aux_init, blocks, imap, gl, leafd, minv, appl, appl_t0, finlist);
+  if (rc) return rc;
+  H->solve_elems = (size_t)Lo.solve_ws;
+  H->scr_build = Lo.scr + 64;
+  if (H->ws.alloc(Lo.ws) != hipSuccess || H->scr.alloc(Lo.scr + 64) != hipSuccess)
+    return fail(HPS_ENOMEM, "device allocation of the operator workspace");
+  HIPCHK(H->imap.upload(imap));
+  HIPCHK(H->aux.upload(aux_init));
+  HIPCHK(H->info.alloc(H->n_info));
+  HIPCHK(hipMemset(H->info.p, 0, sizeof(int32_t) * H->n_info));
+  HIPCHK(H->ipiv.alloc(Lo.ipiv_n + 1));
+  HIPCHK(H->psrc.alloc(Lo.ipiv_n + 1));
+  for (auto &bl : blocks)
+    HIPCHK(hipMemcpy(H->ws.p + bl.first, bl.second.data(), bl.second.size() * sizeof(double),
+                     hipMemcpyHostToDevice));
+  HIPCHK(H->d_gemm.upload(gl.d));
+  HIPCHK(H->d_gemm_t0.upload(gl.t0));
+  HIPCHK(H->d_leaf.upload(leafd));
+  HIPCHK(H->d_minv.upload(minv));
+  HIPCHK(H->d_apply.upload(appl));
+  HIPCHK(H->d_apply_t0.upload(appl_t0));
+  HIPCHK(H->d_finlist.upload(finlist));
+  // keep the coefficients (residuals of mixed-precision solves use them)
+  const size_t ncoef = size_t(H->nleaf) * 6 * p * p;
+  HIPCHK(H->coef.alloc(ncoef));
+  HIPCHK(hipMemcpyAsync(H->coef.p, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, st));
+  Bases bs = make_bases(H.get());
+  bs.d[BUF_IN0] = (void *)coeffs;
+  rc = run_prog(H.get(), H->build_prog, bs, 1, 0, st);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int32_t> info(H->n_info);
+  HIPCHK(hipMemcpy(info.data(), H->info.p, sizeof(int32_t) * H->n_info, hipMemcpyDeviceToHost));
+  for (int i = 0; i < H->n_info; ++i)
+    if (info[i] != 0) {
+      const bool leaf = i < H->nleaf;
+      const std::string what = leaf ? "leaf " + std::to_string(i) : "merge " + std::to_string(i - H->nleaf);
+      if (info[i] > 0)
+        return fail(HPS_ESINGULAR, "zero pivot at step " + std::to_string(info[i]) + " of " + what);
+      return fail(HPS_ENONFINITE, "non-finite pivot at step " + std::to_string(-info[i]) + " of " + what);
+    }
+  if (opts && opts->keep_fp32) {
+    HIPCHK(H->ws32.alloc(H->solve_elems));
+    HIPCHK(launch_cast_f32(H->ws.p, H->ws32.p, (int64_t)H->solve_elems, st));
+    H->has_fp32 = true;
+  }
+  rc = solve_ext_init(H.get());
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  *out = H.release();
+  return HPS_OK;
+}
+
+// Recompute every operator of an existing handle for new coefficients (same
+// tree, p, q): Algorithm 1 again without any device allocation.
+int hps_refactor(hps_handle *H, const double *coeffs, void *stream) {
+  if (!H || !coeffs) return fail(HPS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (H->scr.n < size_t(H->scr_build)) HIPCHK(H->scr.alloc(H->scr_build));
+  HIPCHK(hipMemsetAsync(H->info.p, 0, sizeof(int32_t) * H->n_info, st));
+  const size_t ncoef = size_t(H->nleaf) * 6 * H->p * H->p;
+  HIPCHK(hipMemcpyAsync(H->coef.p, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, st));
+  Bases bs = make_bases(H);
+  bs.d[BUF_IN0] = (void *)coeffs;
+  int rc = run_prog(H, H->build_prog, bs, 1, 0, st);
+  if (rc) return rc;
+  std::vector<int32_t> info(H->n_info);
+  HIPCHK(hipMemcpyAsync(info.data(), H->info.p, sizeof(int32_t) * H->n_info,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < H->n_info; ++i)
+    if (info[i] != 0) {
+      const std::string what = i < H->nleaf ? "leaf " + std::to_string(i)
+                                            : "merge " + std::to_string(i - H->nleaf);
+      if (info[i] > 0)
+        return fail(HPS_ESINGULAR, "zero pivot at step " + std::to_string(info[i]) + " of " + what);
+      return fail(HPS_ENONFINITE, "non-finite pivot at step " + std::to_string(-info[i]) + " of " + what);
+    }
+  if (H->has_fp32) HIPCHK(launch_cast_f32(H->ws.p, H->ws32.p, (int64_t)H->solve_elems, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
+}
+
+void hps_handle_free(hps_handle *h) { delete h; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+static int ensure_solve_buffers(hps_handle *H, int nrhs) {
+  const size_t need_vec = size_t(H->vec_per_rhs) * nrhs;
+  if (H->vec.n < need_vec) HIPCHK(H->vec.alloc(need_vec));
+  const size_t need_part = size_t(H->part_per_rhs) * nrhs + 64;
+  if (H->scr.n < need_part) HIPCHK(H->scr.alloc(std::max<size_t>(need_part, H->scr_build)));
+  return HPS_OK;
+}
+
+// One pass of Algorithm 2 in precision prec (0 FP64, 1 FP32 operators).
+// f, g, u are device arrays in the canonical layouts; jump (optional) adds
+// a flux-jump source on interior Gauss nodes (the refinement correction).
+int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, double *u,
+                   int prec, const double *jump, hipStream_t st) {
+  int rc = ensure_solve_buffers(H, nrhs);
+  if (rc) return rc;
+  Bases bs = make_bases(H);
+  if (prec == 1) {
+    if (!H->has_fp32) return fail(HPS_EINVAL, "handle was built without keep_fp32");
+    bs.d[BUF_WS] = H->ws32.p;
+  }
+  bs.d[BUF_IN0] = (void *)f;
+  bs.d[BUF_IN1] = (void *)g;
+  bs.d[BUF_IN2] = (void *)u;
+  bs.d[BUF_AUX] = (void *)jump;
+  if (jump) {
+    // the w-steps carry an optional B3 source; enable it by switching the
+    // buffer id on a private copy of the program
+    rc = solve_ext_run_up_with_jump(H, bs, nrhs, prec, st);
+  } else {
+    rc = run_prog(H, H->up_prog, bs, nrhs, prec, st);
+  }
+  if (rc) return rc;
+  HIPCHK(launch_copy_map(bs, vref(BUF_VEC, H->ug_off, H->map_bdry, H->vec_per_rhs),
+                         vref(BUF_IN0, 0, -1, H->n_bdry), H->n_bdry, nrhs, st));
+  return run_prog(H, H->down_prog, bs, nrhs, prec, st);
+}
+
+extern "C" int hps_solve(hps_handle *h, const double *f, const double *g, int nrhs, double *u,
+                         const hps_solve_opts *opts) {
+  if (!h || !f || !g || !u) return fail(HPS_EINVAL, "NULL argument");
+  if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  const int prec = opts ? opts->precision : HPS_PREC_FP64;
+  int rc;
+  if (prec == HPS_PREC_MIXED) {
+    rc = solve_ext_mixed(h, f, g, nrhs, u, opts, st);
+  } else {
+    rc = hps_solve_pass(h, f, g, nrhs, u, prec == HPS_PREC_FP32 ? 1 : 0, nullptr, st);
+  }
+  if (rc) return rc;
+  if (opts && opts->u_gauss) {
+    for (int r = 0; r < nrhs; ++r)
+      HIPCHK(hipMemcpyAsync(opts->u_gauss + int64_t(r) * h->pl.n_gauss,
+                            h->vec.p + int64_t(r) * h->vec_per_rhs + h->ug_off,
+                            sizeof(double) * h->pl.n_gauss, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// test hooks (include/hps_debug.h)
+// ---------------------------------------------------------------------------
+extern "C" int hps_debug_gemm(int M, int N, int K, double alpha, const double *A, int lda,
+                              const double *B, int ldb, double *C, int ldc, void *stream) {
+  if (M <= 0 || N <= 0 || K < 0 || !A || !B || !C) return fail(HPS_EINVAL, "bad gemm arguments");
+  hipStream_t st = (hipStream_t)stream;
+  GemmList gl;
+  GemmDesc g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = ref(BUF_IN0, 0, lda); g.B = ref(BUF_IN1, 0, ldb); g.C = ref(BUF_IN2, 0, ldc);
+  g.D = noref(); g.crow = g.ccol = -1; g.alpha = alpha; g.beta = 0.0;
+  gl.add(g);
+  DevArray<GemmDesc> dd;
+  DevArray<int64_t> dt;
+  HIPCHK(dd.upload(gl.d));
+  HIPCHK(dt.upload(gl.t0));
+  Bases bs{};
+  bs.d[BUF_IN0] = (void *)A; bs.d[BUF_IN1] = (void *)B; bs.d[BUF_IN2] = (void *)C;
+  HIPCHK(launch_gemm(dd.p, dt.p, 1, gl.tiles, bs, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, void *stream) {
+  if (n <= 0 || batch <= 0 || !A || !X) return fail(HPS_EINVAL, "bad invert arguments");
+  if (n > 2048) return fail(HPS_EINVAL, "n > 2048");
+  hipStream_t st = (hipStream_t)stream;
+  hps_handle H;
+  const int64_t nn = int64_t(n) * n;
+  // ws: [A copies][zero block][X]
+  HIPCHK(H.ws.alloc(size_t(nn) * (2 * batch + 1)));
+  HIPCHK(hipMemcpyAsync(H.ws.p, A, sizeof(double) * nn * batch, hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_fill(H.ws.p + nn * batch, 0.0, nn, st));
+  const int64_t wsz = std::max<int64_t>(int64_t(kPanelNB) * n, nn);
+  HIPCHK(H.scr.alloc(size_t(wsz) * batch + 64));
+  HIPCHK(H.ipiv.alloc(size_t(n) * batch));
+  HIPCHK(H.psrc.alloc(size_t(n) * batch));
+  HIPCHK(H.info.alloc(batch));
+  HIPCHK(hipMemsetAsync(H.info.p, 0, sizeof(int32_t) * batch, st));
+  std::vector<MergeInvDesc> lev, minv;
+  for (int b = 0; b < batch; ++b) {
+    MergeInvDesc d{};
+    d.Ta = nn * b; d.Tb = nn * batch; d.lda = n; d.ldb = n; d.m = n; d.info = b;
+    d.X = nn * (batch + 1 + b); d.W = wsz * b; d.ipiv = int64_t(n) * b;
+    lev.push_back(d);
+  }
+  GemmList gl;
+  std::vector<Step> prog;
+  emit_inverse_steps(lev, minv, gl, prog);
+  HIPCHK(H.d_minv.upload(minv));
+  HIPCHK(H.d_gemm.upload(gl.d));
+  HIPCHK(H.d_gemm_t0.upload(gl.t0));
+  Bases bs = make_bases(&H);
+  int rc = run_prog(&H, prog, bs, 1, 0, st);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(X, H.ws.p + nn * (batch + 1), sizeof(double) * nn * batch,
+                        hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int32_t> info(batch);
+  HIPCHK(hipMemcpy(info.data(), H.info.p, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
+  for (int b = 0; b < batch; ++b) {
+    if (info[b] > 0) return fail(HPS_ESINGULAR, "zero pivot in matrix " + std::to_string(b));
+    if (info[b] < 0) return fail(HPS_ENONFINITE, "non-finite pivot in matrix " + std::to_string(b));
+  }
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_boxes(const hps_handle *h, int *n_boxes, int32_t *out) {
+  if (!h || !n_boxes) return fail(HPS_EINVAL, "NULL argument");
+  *n_boxes = (int)h->pl.boxes.size();
+  if (!out) return HPS_OK;
+  for (size_t i = 0; i < h->pl.boxes.size(); ++i) {
+    const Box &b = h->pl.boxes[i];
+    int32_t *o = out + 8 * i;
+    o[0] = b.leaf; o[1] = b.leaf_index; o[2] = b.parent; o[3] = b.alpha; o[4] = b.beta;
+    o[5] = (int32_t)b.fin.size(); o[6] = (int32_t)b.nat.size(); o[7] = (int32_t)b.gi.size();
+  }
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_box_nodes(const hps_handle *h, int box, int which, int64_t *out) {
+  if (!h || !out || box < 0 || box >= (int)h->pl.boxes.size()) return fail(HPS_EINVAL, "bad box");
+  const Box &b = h->pl.boxes[box];
+  const std::vector<int64_t> &v = which == 0 ? b.fin : which == 1 ? b.nat : b.gi;
+  std::copy(v.begin(), v.end(), out);
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_box_op(const hps_handle *h, int box, int which, double *out,
+                                int64_t *count) {
+  if (!h || box < 0 || box >= (int)h->pl.boxes.size()) return fail(HPS_EINVAL, "bad box");
+  const Box &b = h->pl.boxes[box];
+  const int64_t ef = (int64_t)b.fin.size(), en = (int64_t)b.nat.size(), m = (int64_t)b.gi.size();
+  const int64_t mi = h->mi, g4 = h->g4;
+  int64_t off = -1, n = 0;
+  switch (which) {
+    case 0: off = h->off_T[box]; n = ef * ef; break;
+    case 1: off = h->off_X[box]; n = m * m; break;
+    case 2:
+      if (b.leaf) { off = h->off_LD[box]; n = mi * g4; }
+      else { off = h->off_S[box]; n = m * en; }
+      break;
+    case 3: if (b.leaf) { off = h->off_LD[box] + g4 * mi; n = mi * mi; } break;
+    case 4: if (b.leaf) { off = h->off_H[box]; n = g4 * mi; } break;
+    default: break;
+  }
+  if (off < 0) return fail(HPS_EINVAL, "operator not stored for this box");
+  if (count) *count = n;
+  if (out) HIPCHK(hipMemcpy(out, h->ws.p + off, sizeof(double) * n, hipMemcpyDeviceToHost));
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_profile(hps_handle *h, int enable) {
+  if (!h) return fail(HPS_EINVAL, "NULL handle");
+  h->prof_on = enable != 0;
+  h->prof_ev.clear();
+  h->prof_used = 0;
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_profile_read(hps_handle *h, int *kinds, double *ms, int max_n,
+                                      int *count) {
+  if (!h || !count) return fail(HPS_EINVAL, "NULL argument");
+  HIPCHK(hipDeviceSynchronize());
+  const int n = std::min<int>(max_n, (int)h->prof_ev.size());
+  for (int i = 0; i < n; ++i) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, h->prof_ev[i].second.first, h->prof_ev[i].second.second));
+    kinds[i] = h->prof_ev[i].first;
+    ms[i] = t;
+  }
+  *count = (int)h->prof_ev.size();
+  h->prof_ev.clear();
+  h->prof_used = 0;
+  return HPS_OK;
+}

@@ -1,0 +1,879 @@
+// HIP kernels of the HPS build and solve stages (gfx950 / CDNA4).
+//
+// * gj_leaf / gj_merge: in-place Gauss-Jordan inversion with partial
+//   pivoting of one matrix per workgroup, the matrix held in registers in a
+//   2-D block-cyclic layout.  Builds F = A_ci,ci^-1 (Sec. 3.3, eq. alpine1)
+//   and X = (T33a - T33b)^-1 (Sec. 4).  Every wavefront searches the pivot
+//   column redundantly from LDS, so one barrier publishes the column and one
+//   publishes the pivot row per elimination step.
+// * gj_panel / gj_colperm: blocked Gauss-Jordan for interface blocks too
+//   large for registers; the rank-NB update between panels is a GEMM.
+// * gemm_f64: grouped FP64 GEMM on MFMA 16x16x4 tiles for the leaf products
+//   (S, H, T of Algorithm 1) and the merge products (S = X R, T update).
+// * apply: grouped matrix-times-vectors of the solve stage (Algorithm 2),
+//   gathered right-hand sides, scattered results, split-K with a fixed
+//   reduction order (results are bitwise reproducible).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "types.hpp"
+
+namespace hps {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int find_desc_tile0(const int64_t *tile0s, int n,
+                                               int64_t tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile0s[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Tiles handed out so that the blocks one XCD receives (block b runs on XCD
+// b % 8) form a contiguous run of logical tiles: neighbouring tiles share
+// operands through that XCD's L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
+  const int64_t per = nblk >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped FP64 GEMM (MFMA)
+// ---------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    const GemmDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
+    int ndesc, int64_t ntiles, Bases bs) {
+  __shared__ double As[GBK][GBM + 1];
+  __shared__ double Bs[GBK][GBN + 1];
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= ntiles) return;
+  const GemmDesc &d = descs[find_desc_tile0(tile0s, ndesc, tile)];
+  const int64_t t = tile - d.tile0;
+  const int row0 = int(t / d.tn) * GBM, col0 = int(t % d.tn) * GBN;
+  const int M = d.M, N = d.N, K = d.K;
+  const double *A = (const double *)bs.d[d.A.buf] + d.A.off;
+  const double *B = (const double *)bs.d[d.B.buf] + d.B.off;
+  const int lda = d.A.ld, ldb = d.B.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid & 1, wn = wid >> 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += GBK) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = tid & 63, kk = (tid >> 6) + 4 * s;
+      const int gr = row0 + r, gk = k0 + kk;
+      As[kk][r] = (gr < M && gk < K) ? A[gr + int64_t(gk) * lda] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = tid & 15, c = (tid >> 4) + 16 * s;
+      const int gk = k0 + kk, gc = col0 + c;
+      Bs[kk][c] = (gk < K && gc < N) ? B[gk + int64_t(gc) * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      const int ka = kk + (lane >> 4), li = lane & 15;
+      const double a0 = As[ka][wm * 32 + li];
+      const double a1 = As[ka][wm * 32 + 16 + li];
+      const double b0 = Bs[ka][wn * 32 + li];
+      const double b1 = Bs[ka][wn * 32 + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double *C = (double *)bs.d[d.C.buf] + d.C.off;
+  const double *D = d.D.buf >= 0 ? (const double *)bs.d[d.D.buf] + d.D.off : nullptr;
+  const int32_t *crow = d.crow >= 0 ? bs.imap + d.crow : nullptr;
+  const int32_t *ccol = d.ccol >= 0 ? bs.imap + d.ccol : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // f64 16x16x4 result layout: lane l, register v holds row (l >> 4) + 4 v,
+        // column l & 15
+        const int row = row0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
+        const int col = col0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double val = d.alpha * acc[i][j][v];
+          if (D) val += d.beta * D[row + int64_t(col) * d.D.ld];
+          const int64_t cr = crow ? crow[row] : row;
+          const int64_t cc = ccol ? ccol[col] : col;
+          C[cr + cc * d.C.ld] = val;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident Gauss-Jordan inversion
+// ---------------------------------------------------------------------------
+// Threads per workgroup of the register-resident kernels: TR*TC rounded up to
+// whole wavefronts, so every wavefront of the pivot search has all lanes
+// active; the extra threads own no rows or columns.
+template <int TR, int TC>
+constexpr int gj_threads() { return (TR * TC + 63) / 64 * 64; }
+
+template <int TR, int TC, int RA, int CB>
+__device__ __forceinline__ void gj_owner(int tid, int &tr, int &tc) {
+  if (tid < TR * TC) { tr = tid % TR; tc = tid / TR; }
+  else { tr = TR * RA; tc = TC * CB; }
+}
+
+template <int TR, int TC, int RA, int CB>
+struct GJShared {
+  double colbuf[2][TR * RA];
+  double rowbuf[TC * CB];
+  int pivrow[TR * RA];
+  int stepof[TR * RA];
+  unsigned char used[TR * RA];
+  int info;
+};
+
+// Thread (tr, tc) owns rows tr + TR*i and columns tc + TC*b.  On exit the
+// registers hold the swept matrix M with M[r_k][k'] = inv[k][r_k'] where r_k
+// is the pivot row of step k.
+template <int TR, int TC, int RA, int CB>
+__device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
+                                        const int tr, const int tc,
+                                        GJShared<TR, TC, RA, CB> &sh) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int i = tid; i < TR * RA; i += blockDim.x) sh.used[i] = 0;
+  if (tid == 0) sh.info = 0;
+  if (tc == 0) {
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      const int row = tr + TR * i;
+      if (row < n) sh.colbuf[0][row] = a[i][0];
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double *cb = sh.colbuf[k & 1];
+    double best = -3.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < n; i += 64) {
+      if (!sh.used[i]) {
+        const double x = cb[i];
+        const double v = (x != x) ? -1.0 : fabs(x);
+        if (v > best) { best = v; bi = i; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int r = __builtin_amdgcn_readfirstlane(bi);
+    const double piv = cb[r];
+    const int ir = r / TR;
+    if (tr == r - ir * TR) {
+#pragma unroll
+      for (int i = 0; i < RA; ++i)
+        if (i == ir) {
+#pragma unroll
+          for (int b = 0; b < CB; ++b) {
+            const int col = tc + TC * b;
+            if (col < n) sh.rowbuf[col] = a[i][b];
+          }
+        }
+    }
+    const bool ok = (piv != 0.0) && isfinite(piv);
+    if (tid == 0) {
+      sh.pivrow[k] = r;
+      sh.stepof[r] = k;
+      if (!ok && sh.info == 0) sh.info = isfinite(piv) ? (k + 1) : -(k + 1);
+    }
+    __syncthreads();
+    const double ip = ok ? 1.0 / piv : 0.0;
+    double s[CB];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = tc + TC * b;
+      s[b] = (col < n) ? sh.rowbuf[col] * ip : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      const int row = tr + TR * i;
+      const double f = (row < n) ? cb[row] : 0.0;
+#pragma unroll
+      for (int b = 0; b < CB; ++b) a[i][b] = fma(-f, s[b], a[i][b]);
+    }
+    const int kb = k / TC;
+    const bool kown = (tc == k - kb * TC);
+    if (kown) {
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+        if (b == kb) {
+#pragma unroll
+          for (int i = 0; i < RA; ++i) {
+            const int row = tr + TR * i;
+            a[i][b] = (row < n) ? -cb[row] * ip : 0.0;
+          }
+        }
+    }
+    if (tr == r - ir * TR) {
+#pragma unroll
+      for (int i = 0; i < RA; ++i)
+        if (i == ir) {
+#pragma unroll
+          for (int b = 0; b < CB; ++b) a[i][b] = (kown && b == kb) ? ip : s[b];
+        }
+    }
+    if (tid == 0) sh.used[r] = 1;
+    if (k + 1 < n) {
+      const int k1 = k + 1, kb1 = k1 / TC;
+      if (tc == k1 - kb1 * TC) {
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+          if (b == kb1) {
+#pragma unroll
+            for (int i = 0; i < RA; ++i) {
+              const int row = tr + TR * i;
+              if (row < n) sh.colbuf[k1 & 1][row] = a[i][b];
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int TR, int TC, int RA, int CB>
+__device__ __forceinline__ void gj_store(const double (&a)[RA][CB], const int n,
+                                         const int tr, const int tc,
+                                         const GJShared<TR, TC, RA, CB> &sh,
+                                         double *X, const int ldx) {
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = tr + TR * i;
+    if (row >= n) continue;
+    const int64_t orow = sh.stepof[row];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = tc + TC * b;
+      if (col < n) X[orow + int64_t(sh.pivrow[col]) * ldx] = a[i][b];
+    }
+  }
+}
+
+// Leaf: A_ci,ci and A_ci,ce of
+//   A = -C11 Dx^2 - 2 C12 Dx Dy - C22 Dy^2 + C1 Dx + C2 Dy + C   (Sec. 3.2)
+// from the nodal coefficients and the reference matrix Dh (p x p, row-major)
+// and its square Dh2.
+template <int P, int TR, int TC, int RA, int CB>
+__global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
+    const LeafDesc *__restrict__ descs, int nleaf, Bases bs,
+    const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
+    const int32_t *__restrict__ ice, int me, int32_t *__restrict__ info) {
+  constexpr int PI = P - 2, MI = PI * PI;
+  __shared__ GJShared<TR, TC, RA, CB> sh;
+  __shared__ double cf[6][P * P];
+  __shared__ double Dh[P * P], Dh2[P * P];
+  const int leaf = blockIdx.x;
+  if (leaf >= nleaf) return;
+  const LeafDesc &d = descs[leaf];
+  const double *coef = (const double *)bs.d[BUF_IN0] + d.coef;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 6 * P * P; i += blockDim.x) cf[i / (P * P)][i % (P * P)] = coef[i];
+  for (int i = tid; i < P * P; i += blockDim.x) { Dh[i] = Dh_g[i]; Dh2[i] = Dh2_g[i]; }
+  __syncthreads();
+  const double sx = d.sx, sy = d.sy;
+  auto entry = [&](int ga, int gb) -> double {
+    // ga: grid index of the collocation row, gb: grid index of the column
+    const int iy = ga / P, ix = ga - iy * P, jy = gb / P, jx = gb - jy * P;
+    double v = -2.0 * cf[1][ga] * sx * sy * Dh[iy * P + jy] * Dh[ix * P + jx];
+    if (iy == jy) v += -cf[0][ga] * sx * sx * Dh2[ix * P + jx] + cf[3][ga] * sx * Dh[ix * P + jx];
+    if (ix == jx) v += -cf[2][ga] * sy * sy * Dh2[iy * P + jy] + cf[4][ga] * sy * Dh[iy * P + jy];
+    if (ga == gb) v += cf[5][ga];
+    return v;
+  };
+  auto grid_of = [](int a) { const int y = a / PI; return (y + 1) * P + (a - y * PI) + 1; };
+  // A_ci,ce (mi x me, column-major) for the leaf products
+  double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
+  for (int idx = tid; idx < MI * me; idx += blockDim.x) {
+    const int a = idx % MI, e = idx / MI;
+    Aie[idx] = entry(grid_of(a), ice[e]);
+  }
+  int tr, tc;
+  gj_owner<TR, TC, RA, CB>(tid, tr, tc);
+  double a[RA][CB];
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = tr + TR * i;
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = tc + TC * b;
+      a[i][b] = (row < MI && col < MI) ? entry(grid_of(row), grid_of(col)) : 0.0;
+    }
+  }
+  gj_core<TR, TC, RA, CB>(a, MI, tr, tc, sh);
+  double *F = (double *)bs.d[BUF_WS] + d.F;
+  gj_store<TR, TC, RA, CB>(a, MI, tr, tc, sh, F, MI);
+  if (tid == 0) info[d.info] = sh.info;
+}
+
+template <int TR, int TC, int RA, int CB>
+__global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_merge_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, Bases bs,
+    int32_t *__restrict__ info) {
+  __shared__ GJShared<TR, TC, RA, CB> sh;
+  const int idx = blockIdx.x;
+  if (idx >= nd) return;
+  const MergeInvDesc &d = descs[idx];
+  const double *Ta = (const double *)bs.d[BUF_WS] + d.Ta;
+  const double *Tb = (const double *)bs.d[BUF_WS] + d.Tb;
+  const int n = d.m;
+  const int tid = threadIdx.x;
+  int tr, tc;
+  gj_owner<TR, TC, RA, CB>(tid, tr, tc);
+  double a[RA][CB];
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = tr + TR * i;
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = tc + TC * b;
+      a[i][b] = (row < n && col < n)
+                    ? Ta[row + int64_t(col) * d.lda] - Tb[row + int64_t(col) * d.ldb]
+                    : 0.0;
+    }
+  }
+  gj_core<TR, TC, RA, CB>(a, n, tr, tc, sh);
+  gj_store<TR, TC, RA, CB>(a, n, tr, tc, sh, (double *)bs.d[BUF_WS] + d.X, n);
+  if (tid == 0) info[d.info] = sh.info;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan for large interface blocks
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void zdiff_kernel(const MergeInvDesc *__restrict__ descs,
+                                                    int nd, Bases bs) {
+  const MergeInvDesc &d = descs[blockIdx.y];
+  const int n = d.m;
+  const double *Ta = (const double *)bs.d[BUF_WS] + d.Ta;
+  const double *Tb = (const double *)bs.d[BUF_WS] + d.Tb;
+  double *X = (double *)bs.d[BUF_WS] + d.X;
+  const int64_t tot = int64_t(n) * n;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t col = e / n, row = e - col * n;
+    X[e] = Ta[row + col * d.lda] - Tb[row + col * d.ldb];
+  }
+}
+
+// One workgroup per matrix: unblocked Gauss-Jordan on the NB columns
+// [kb, kb+NB) held in registers (row t + 512 i owned by thread t), pivot rows
+// chosen among rows >= k, rows swapped across the whole matrix, then the old
+// pivot rows outside the panel copied to W (NB x m, ld NB) for the update.
+template <int NB, int RPT>
+__global__ __launch_bounds__(512) void gj_panel_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, int kb, Bases bs,
+    int32_t *__restrict__ ipiv_all, int32_t *__restrict__ info) {
+  __shared__ double wbest[8];
+  __shared__ int wbi[8];
+  __shared__ double prow[NB];
+  __shared__ double srow[NB];
+  __shared__ int s_r;
+  __shared__ int s_piv[NB];
+  const MergeInvDesc &d = descs[blockIdx.x];
+  const int n = d.m;
+  if (kb >= n) return;
+  const int nbv = min(NB, n - kb);
+  double *A = (double *)bs.d[BUF_WS] + d.X;
+  int32_t *ipiv = ipiv_all + d.ipiv;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double pan[RPT][NB];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = tid + 512 * i;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      pan[i][c] = (row < n && c < nbv) ? A[row + int64_t(kb + c) * n] : 0.0;
+  }
+  int first_bad = 0;
+  for (int c = 0; c < nbv; ++c) {
+    const int k = kb + c;
+    double best = -3.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + 512 * i;
+      if (row >= k && row < n) {
+        double x = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) if (cc == c) x = pan[i][cc];
+        const double v = (x != x) ? -1.0 : fabs(x);
+        if (v > best || (v == best && row < bi)) { best = v; bi = row; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { wbest[wid] = best; wbi[wid] = bi; }
+    __syncthreads();
+    if (wid == 0) {
+      double b2 = lane < 8 ? wbest[lane] : -3.0;
+      int i2 = lane < 8 ? wbi[lane] : 0x7fffffff;
+#pragma unroll
+      for (int off = 32; off; off >>= 1) {
+        const double ob = __shfl_xor(b2, off);
+        const int oi = __shfl_xor(i2, off);
+        if (ob > b2 || (ob == b2 && oi < i2)) { b2 = ob; i2 = oi; }
+      }
+      if (lane == 0) { s_r = i2; s_piv[c] = i2; ipiv[k] = i2; }
+    }
+    __syncthreads();
+    const int r = s_r;
+    // exchange rows k and r inside the panel; prow = new row k
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + 512 * i;
+      if (row == r) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) prow[cc] = pan[i][cc];
+      }
+      if (row == k) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) srow[cc] = pan[i][cc];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + 512 * i;
+      if (row == r && r != k) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) pan[i][cc] = srow[cc];
+      }
+      if (row == k) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) pan[i][cc] = prow[cc];
+      }
+    }
+    double piv = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) if (cc == c) piv = prow[cc];
+    const bool ok = (piv != 0.0) && isfinite(piv);
+    if (!ok && first_bad == 0) first_bad = isfinite(piv) ? (k + 1) : -(k + 1);
+    const double ip = ok ? 1.0 / piv : 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + 512 * i;
+      double f = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) if (cc == c) f = pan[i][cc];
+      if (row == k) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) pan[i][cc] = (cc == c) ? ip : prow[cc] * ip;
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc)
+          pan[i][cc] = (cc == c) ? -f * ip : fma(-f, prow[cc] * ip, pan[i][cc]);
+      }
+    }
+    __syncthreads();
+  }
+  // write the panel back
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = tid + 512 * i;
+    if (row < n) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nbv) A[row + int64_t(kb + c) * n] = pan[i][c];
+    }
+  }
+  // apply the row interchanges outside the panel, in order
+  for (int c = 0; c < nbv; ++c) {
+    const int k = kb + c, r = s_piv[c];
+    if (r != k) {
+      for (int j = tid; j < n; j += 512) {
+        if (j >= kb && j < kb + nbv) continue;
+        const double t0 = A[k + int64_t(j) * n];
+        A[k + int64_t(j) * n] = A[r + int64_t(j) * n];
+        A[r + int64_t(j) * n] = t0;
+      }
+    }
+    __syncthreads();
+  }
+  // W = pivot rows outside the panel (old values), NB x n, ld NB
+  double *W = (double *)bs.d[BUF_SCR] + d.W;
+  for (int e = tid; e < NB * n; e += 512) {
+    const int c = e % NB, j = e / NB;
+    W[e] = (c < nbv && (j < kb || j >= kb + nbv)) ? A[kb + c + int64_t(j) * n] : 0.0;
+  }
+  if (tid == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
+}
+
+// Final column interchanges of the blocked Gauss-Jordan: X(:, j) = Y(:, src(j))
+// where src follows the interchanges in reverse order; Y is a copy in scratch.
+__global__ __launch_bounds__(1024) void gj_colperm_src_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, int32_t *__restrict__ ipiv_all,
+    int32_t *__restrict__ src_all) {
+  const MergeInvDesc &d = descs[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const int n = d.m;
+  int32_t *src = src_all + d.ipiv;
+  const int32_t *ipiv = ipiv_all + d.ipiv;
+  for (int j = 0; j < n; ++j) src[j] = j;
+  for (int k = n - 1; k >= 0; --k) {
+    const int r = ipiv[k];
+    const int32_t t0 = src[k];
+    src[k] = src[r];
+    src[r] = t0;
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_colperm_copy_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, Bases bs, int to_scratch,
+    const int32_t *__restrict__ src_all) {
+  const MergeInvDesc &d = descs[blockIdx.y];
+  const int n = d.m;
+  double *X = (double *)bs.d[BUF_WS] + d.X;
+  double *Y = (double *)bs.d[BUF_SCR] + d.W;   // scratch copy (n x n)
+  const int32_t *src = src_all + d.ipiv;
+  const int64_t tot = int64_t(n) * n;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    if (to_scratch) {
+      Y[e] = X[e];
+    } else {
+      const int64_t col = e / n, row = e - col * n;
+      X[e] = Y[row + int64_t(src[col]) * n];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve-stage applies
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double vload(const Bases &bs, const VRef &v, int64_t k,
+                                        int r) {
+  const int64_t idx = v.map >= 0 ? bs.imap[v.map + k] : k;
+  return ((const double *)bs.d[v.buf])[v.off + idx + r * v.stride];
+}
+
+template <typename TA, typename TC_, int NR>
+__global__ __launch_bounds__(256) void apply_kernel(
+    const ApplyDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
+    int ndesc, int64_t ntiles, Bases bs, int nrhs) {
+  constexpr int KC = 256;
+  __shared__ TC_ Bsh[KC][NR];
+  __shared__ TC_ red[4][64][NR];
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= ntiles) return;
+  const ApplyDesc &d = descs[find_desc_tile0(tile0s, ndesc, tile)];
+  const int64_t t = tile - d.tile0;
+  const int rbi = int(t % d.rb), slice = int(t / d.rb);
+  const int K = d.K1 + (d.mode == 0 ? d.K2 : 0);
+  const int kper = (K + d.ksl - 1) / d.ksl;
+  const int k0 = slice * kper, k1 = min(K, k0 + kper);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int row = rbi * 64 + lane;
+  const int r0 = blockIdx.y * NR;
+  const TA *A = (const TA *)bs.d[d.abuf] + d.aoff;
+  const int lda = d.lda;
+  TC_ acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = TC_(0);
+  for (int kc = k0; kc < k1; kc += KC) {
+    const int kn = min(KC, k1 - kc);
+    for (int e = tid; e < kn * NR; e += 256) {
+      const int kk = e % kn, r = e / kn, k = kc + kk, rg = r0 + r;
+      double v = 0.0;
+      if (rg < nrhs) {
+        if (d.mode == 0) {
+          v = k < d.K1 ? vload(bs, d.B1, k, rg) : vload(bs, d.B2, k - d.K1, rg);
+        } else {
+          v = vload(bs, d.B1, k, rg) - vload(bs, d.B2, k, rg);
+          if (d.B3.buf >= 0) v += vload(bs, d.B3, k, rg);
+        }
+      }
+      Bsh[kk][r] = TC_(v);
+    }
+    __syncthreads();
+    const int q4 = (kn + 3) >> 2, ka = wid * q4, kz = min(kn, ka + q4);
+    if (row < d.M) {
+      const TA *Ap = A + row + int64_t(kc) * lda;
+#pragma unroll 8
+      for (int kk = ka; kk < kz; ++kk) {
+        const TC_ av = TC_(Ap[int64_t(kk) * lda]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = fma(av, Bsh[kk][r], acc[r]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[wid][lane][r] = acc[r];
+  __syncthreads();
+  if (wid == 0 && row < d.M) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int rg = r0 + r;
+      if (rg >= nrhs) continue;
+      const double s = double(red[0][lane][r]) + double(red[1][lane][r]) +
+                       double(red[2][lane][r]) + double(red[3][lane][r]);
+      if (d.ksl == 1) {
+        double val = d.alpha * s;
+        if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg);
+        const int64_t ci = d.C.map >= 0 ? bs.imap[d.C.map + row] : row;
+        ((double *)bs.d[d.C.buf])[d.C.off + ci + rg * d.C.stride] = val;
+      } else {
+        ((double *)bs.d[BUF_SCR])[d.part * nrhs + (int64_t(slice) * nrhs + rg) * d.M + row] = s;
+      }
+    }
+  }
+}
+
+// Sum the split-K partials of each descriptor in slice order.
+__global__ __launch_bounds__(256) void apply_finalize_kernel(
+    const ApplyDesc *__restrict__ descs, const int32_t *__restrict__ list, int nlist,
+    Bases bs, int nrhs) {
+  const ApplyDesc &d = descs[list[blockIdx.y]];
+  const int64_t tot = int64_t(d.M) * nrhs;
+  const double *part = (const double *)bs.d[BUF_SCR] + d.part * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int rg = int(e / d.M), row = int(e - int64_t(rg) * d.M);
+    double s = 0.0;
+    for (int sl = 0; sl < d.ksl; ++sl) s += part[(int64_t(sl) * nrhs + rg) * d.M + row];
+    double val = d.alpha * s;
+    if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg);
+    const int64_t ci = d.C.map >= 0 ? bs.imap[d.C.map + row] : row;
+    ((double *)bs.d[d.C.buf])[d.C.off + ci + rg * d.C.stride] = val;
+  }
+}
+
+// dst(map_d(i), r) = src(map_s(i), r) for i < n, r < nrhs
+__global__ __launch_bounds__(256) void copy_map_kernel(Bases bs, VRef dst, VRef src,
+                                                       int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(e / n);
+    const int64_t i = e - int64_t(r) * n;
+    const double v = vload(bs, src, i, r);
+    const int64_t di = dst.map >= 0 ? bs.imap[dst.map + i] : i;
+    ((double *)bs.d[dst.buf])[dst.off + di + r * dst.stride] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void cast_f32_kernel(const double *__restrict__ src,
+                                                       float *__restrict__ dst, int64_t n) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * blockDim.x)
+    dst[e] = float(src[e]);
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double *__restrict__ dst, double v, int64_t n) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * blockDim.x)
+    dst[e] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned grid_1d(int64_t n, int64_t cap = 65536) {
+  int64_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+hipError_t launch_gemm(const GemmDesc *descs, const int64_t *tile0s, int ndesc,
+                       int64_t ntiles, const Bases &bs, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  const int64_t nblk = (ntiles + 7) / 8 * 8;
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, descs,
+                     tile0s, ndesc, ntiles, bs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
+                          const double *Dh, const double *Dh2, const int32_t *ice,
+                          int me, int32_t *info, hipStream_t st) {
+  if (nleaf <= 0) return hipSuccess;
+  switch (p) {
+    case 16:
+      hipLaunchKernelGGL((gj_leaf_kernel<16, 28, 36, 7, 6>), dim3(nleaf), dim3(gj_threads<28, 36>()), 0,
+                         st, descs, nleaf, bs, Dh, Dh2, ice, me, info);
+      break;
+    case 12:
+      hipLaunchKernelGGL((gj_leaf_kernel<12, 20, 20, 5, 5>), dim3(nleaf), dim3(gj_threads<20, 20>()), 0, st,
+                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+      break;
+    case 10:
+      hipLaunchKernelGGL((gj_leaf_kernel<10, 8, 8, 8, 8>), dim3(nleaf), dim3(64), 0, st,
+                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+      break;
+    case 8:
+      hipLaunchKernelGGL((gj_leaf_kernel<8, 8, 8, 5, 5>), dim3(nleaf), dim3(64), 0, st,
+                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+      break;
+    case 6:
+      hipLaunchKernelGGL((gj_leaf_kernel<6, 8, 8, 2, 2>), dim3(nleaf), dim3(64), 0, st,
+                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int gj_leaf_supported(int p) { return p == 16 || p == 12 || p == 10 || p == 8 || p == 6; }
+
+// size classes of the register-resident interface inversion
+int gj_merge_class(int m) {
+  if (m <= 32) return 0;
+  if (m <= 64) return 1;
+  if (m <= 128) return 2;
+  if (m <= 196) return 3;
+  return -1;
+}
+
+hipError_t launch_gj_merge(int cls, const MergeInvDesc *descs, int nd, const Bases &bs,
+                           int32_t *info, hipStream_t st) {
+  if (nd <= 0) return hipSuccess;
+  switch (cls) {
+    case 0:
+      hipLaunchKernelGGL((gj_merge_kernel<8, 8, 4, 4>), dim3(nd), dim3(64), 0, st, descs, nd,
+                         bs, info);
+      break;
+    case 1:
+      hipLaunchKernelGGL((gj_merge_kernel<8, 8, 8, 8>), dim3(nd), dim3(64), 0, st, descs, nd,
+                         bs, info);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gj_merge_kernel<16, 16, 8, 8>), dim3(nd), dim3(256), 0, st, descs,
+                         nd, bs, info);
+      break;
+    case 3:
+      hipLaunchKernelGGL((gj_merge_kernel<28, 36, 7, 6>), dim3(nd), dim3(gj_threads<28, 36>()), 0, st,
+                         descs, nd, bs, info);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zdiff(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                        hipStream_t st) {
+  if (nd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zdiff_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd), dim3(256),
+                     0, st, descs, nd, bs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
+                           const Bases &bs, int32_t *ipiv, int32_t *info, hipStream_t st) {
+  if (nd <= 0) return hipSuccess;
+  if (maxm <= 1024)
+    hipLaunchKernelGGL((gj_panel_kernel<kPanelNB, 2>), dim3(nd), dim3(512), 0, st, descs, nd,
+                       kb, bs, ipiv, info);
+  else if (maxm <= 2048)
+    hipLaunchKernelGGL((gj_panel_kernel<kPanelNB, 4>), dim3(nd), dim3(512), 0, st, descs, nd,
+                       kb, bs, ipiv, info);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                             int32_t *ipiv, int32_t *src, hipStream_t st) {
+  if (nd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gj_colperm_src_kernel, dim3(nd), dim3(64), 0, st, descs, nd, ipiv, src);
+  hipLaunchKernelGGL(gj_colperm_copy_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
+                     dim3(256), 0, st, descs, nd, bs, 1, src);
+  hipLaunchKernelGGL(gj_colperm_copy_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
+                     dim3(256), 0, st, descs, nd, bs, 0, src);
+  return hipGetLastError();
+}
+
+template <typename TA, typename TC_>
+static void launch_apply_t(const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
+                           int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st) {
+  const int64_t nblk = (ntiles + 7) / 8 * 8;
+  if (nrhs >= 8) {
+    dim3 g(unsigned(nblk), unsigned((nrhs + 7) / 8));
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 8>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+                       ntiles, bs, nrhs);
+  } else if (nrhs >= 4) {
+    dim3 g(unsigned(nblk), unsigned((nrhs + 3) / 4));
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 4>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+                       ntiles, bs, nrhs);
+  } else if (nrhs >= 2) {
+    dim3 g(unsigned(nblk), unsigned((nrhs + 1) / 2));
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 2>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+                       ntiles, bs, nrhs);
+  } else {
+    dim3 g(unsigned(nblk), 1);
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 1>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+                       ntiles, bs, nrhs);
+  }
+}
+
+hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
+                        int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (prec == 0)
+    launch_apply_t<double, double>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+  else
+    launch_apply_t<float, float>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_finalize(const ApplyDesc *descs, const int32_t *list, int nlist,
+                                 int64_t maxm, const Bases &bs, int nrhs, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(apply_finalize_kernel, dim3(grid_1d(maxm * nrhs, 256), nlist), dim3(256),
+                     0, st, descs, list, nlist, bs, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_map(const Bases &bs, const VRef &dst, const VRef &src, int64_t n,
+                           int nrhs, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_map_kernel, dim3(grid_1d(n * nrhs)), dim3(256), 0, st, bs, dst, src,
+                     n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cast_f32_kernel, dim3(grid_1d(n)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_1d(n)), dim3(256), 0, st, dst, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace hps

@@ -1,0 +1,38 @@
+// Launchers of the HIP kernels (kernels.hip).  All launches are asynchronous
+// on the given stream; descriptor arrays live in device memory.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "types.hpp"
+
+namespace hps {
+
+constexpr int kPanelNB = 16;   // panel width of the blocked Gauss-Jordan
+
+hipError_t launch_gemm(const GemmDesc *descs, const int64_t *tile0s, int ndesc,
+                       int64_t ntiles, const Bases &bs, hipStream_t st);
+int gj_leaf_supported(int p);
+hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
+                          const double *Dh, const double *Dh2, const int32_t *ice,
+                          int me, int32_t *info, hipStream_t st);
+int gj_merge_class(int m);
+hipError_t launch_gj_merge(int cls, const MergeInvDesc *descs, int nd, const Bases &bs,
+                           int32_t *info, hipStream_t st);
+hipError_t launch_zdiff(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                        hipStream_t st);
+hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
+                           const Bases &bs, int32_t *ipiv, int32_t *info, hipStream_t st);
+hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                             int32_t *ipiv, int32_t *src, hipStream_t st);
+hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
+                        int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st);
+hipError_t launch_apply_finalize(const ApplyDesc *descs, const int32_t *list, int nlist,
+                                 int64_t maxm, const Bases &bs, int nrhs, hipStream_t st);
+hipError_t launch_copy_map(const Bases &bs, const VRef &dst, const VRef &src, int64_t n,
+                           int nrhs, hipStream_t st);
+hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t st);
+
+}  // namespace hps

@@ -1,0 +1,87 @@
+// Descriptor records shared by the host planner and the HIP kernels.
+//
+// Every matrix is column-major.  A location is (buffer id, element offset);
+// the kernels receive the buffer base pointers in a small by-value table, so
+// one descriptor list serves any set of caller buffers.
+#pragma once
+#include <cstdint>
+
+namespace hps {
+
+enum BufId : int32_t {
+  BUF_WS = 0,     // FP64 operator workspace (owned by the handle)
+  BUF_SCR = 1,    // FP64 scratch (build temporaries, split-K partials)
+  BUF_IN0 = 2,    // per-call inputs/outputs (coeffs, f, g, u, ...)
+  BUF_IN1 = 3,
+  BUF_IN2 = 4,
+  BUF_VEC = 5,    // per-solve work vectors (h / w slots, global u, residuals)
+  BUF_W32 = 6,    // FP32 operator copies
+  BUF_AUX = 7,
+  NBUF = 8
+};
+
+struct Bases {
+  void *d[NBUF];
+  const int32_t *imap;  // integer maps (gather/scatter lists)
+};
+
+struct Ref {
+  int32_t buf;  // < 0: absent
+  int32_t ld;
+  int64_t off;
+};
+
+// C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * D(i,j), written at
+// C[crow(i) + ccol(j) * ldc] (maps optional).
+struct GemmDesc {
+  int32_t M, N, K, tn;
+  int64_t tile0;
+  Ref A, B, C, D;
+  int64_t crow, ccol;   // offsets into imap, -1 = identity
+  double alpha, beta;
+};
+
+// Leaf interior block: assemble A_ci,ci and A_ci,ce from the nodal
+// coefficients, invert A_ci,ci in place (Gauss-Jordan, partial pivoting).
+struct LeafDesc {
+  int64_t coef;   // BUF_IN0 offset of the leaf's [6][p*p] coefficients
+  int64_t F;      // BUF_WS offset of F (mi x mi, ld mi)
+  int64_t Aie;    // BUF_SCR offset of A_ci,ce (mi x me, ld mi)
+  double sx, sy;  // 2/hx, 2/hy
+  int32_t info;   // slot in the info array
+  int32_t pad;
+};
+
+// Interface block of a merge: X = (T33a - T33b)^-1.
+struct MergeInvDesc {
+  int64_t Ta, Tb;   // BUF_WS offsets of the T33 blocks
+  int32_t lda, ldb;
+  int32_t m, info;
+  int64_t X;        // BUF_WS offset, ld m
+  int64_t W;        // BUF_SCR offset of the blocked path's pivot-row panel
+  int64_t ipiv;     // imap-independent int scratch offset (blocked path)
+};
+
+// Vector operand of the solve-stage applies: element (k, r) at
+// base[buf][off + (map >= 0 ? imap[map + k] : k) + r * stride].
+struct VRef {
+  int32_t buf;
+  int32_t pad;
+  int64_t off, map, stride;
+};
+
+// C(map(i), r) = alpha * sum_k A(i,k) B(k,r) + beta * D(i,r)
+// B rows k < K1 come from B1, k >= K1 from B2 (mode 0); in mode 1
+// B(k) = B1(k) - B2(k) (+ B3(k) if present), K = K1.
+struct ApplyDesc {
+  int32_t M, K1, K2, mode;
+  int32_t ksl, rb;      // k-slices and 64-row blocks
+  int64_t tile0;
+  int32_t abuf, lda;
+  int64_t aoff;
+  VRef B1, B2, B3, C, D;
+  double alpha, beta;
+  int64_t part;         // split-K partials start at BUF_SCR[part * nrhs]
+};
+
+}  // namespace hps

@@ -1,0 +1,129 @@
+"""Per-kernel GPU parity through the test hooks: the MFMA GEMM, the
+Gauss-Jordan inversions and the stored leaf / merge operators of a build
+against the oracle's operators (unit parity <= 1e-12 relative)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from gpu_cases import lib_inputs, relerr, to_dev
+from oracle_cases import make_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1612_02736_amd as H
+    H.lib()
+    return H
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (64, 64, 16), (196, 60, 196),
+                                   (100, 300, 37), (130, 70, 0)])
+def test_gemm_matches_numpy(M, N, K):
+    import torch
+    from paper_1612_02736_amd.hps import debug_gemm
+    rng = np.random.default_rng(M * 1000 + N + K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    print(f"gemm {M}x{N}x{K}", flush=True)
+    C = debug_gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), alpha=-0.5)
+    ref = -0.5 * A @ B
+    np.testing.assert_allclose(C.cpu().numpy(), ref, atol=1e-13 * max(1, np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("n", [1, 5, 32, 33, 64, 100, 128, 196, 197, 240, 500])
+def test_inverse_matches_numpy(n):
+    import torch
+    from paper_1612_02736_amd.hps import debug_invert
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((3, n, n)) + 2.0 * np.sqrt(n) * np.eye(n) * (rng.random((3, 1, 1)) > 0.5)
+    print(f"invert n={n}", flush=True)
+    X = debug_invert(torch.from_numpy(A).cuda()).cpu().numpy()
+    for b in range(3):
+        ref = np.linalg.inv(A[b])
+        assert relerr(X[b], ref) < 1e-10 * np.linalg.cond(A[b]) / n
+
+
+def _build_pair(nx, ny, p, q=None, refine=None):
+    H = _H()
+    q = q or p - 1
+    t = H.Tree(0, 1, 0, 1, nx, ny)
+    ot = oracle.Tree.uniform(0, 1, 0, 1, nx, ny)
+    if refine:
+        t.refine_point(0, *refine)
+        ot.refine_point(0, *refine)
+    sol = W.FourierSolution(1)
+    coeffs, _, _, _ = lib_inputs(t, p, q, W.varcoeff, sol)
+    s = H.Solver(t, to_dev(coeffs), p, q)
+    oc, _, _, _ = make_inputs(ot, p, q, W.varcoeff, sol)
+    ops = oracle.build(ot, oc, p, q)
+    return H, s, ot, ops, p, q
+
+
+@pytest.mark.parametrize("nx,ny,p", [(2, 2, 8), (2, 2, 16), (4, 4, 12)])
+def test_leaf_operators(nx, ny, p):
+    H, s, ot, ops, p, q = _build_pair(nx, ny, p)
+    from paper_1612_02736_amd.hps import debug_boxes, debug_box_nodes, debug_box_op
+    boxes = debug_boxes(s)
+    mi, g4 = (p - 2) ** 2, 4 * q
+    leaves = ot.leaves
+    for b, info in enumerate(boxes):
+        if not info[0]:
+            continue
+        li = info[1]
+        ob = leaves[li]
+        o = ops.box[ob.id]
+        fin = debug_box_nodes(s, b, 0)
+        pos = {j: i for i, j in enumerate(ob.ge)}
+        perm = np.array([pos[j] for j in fin])
+        I_ci = o["I_ci"]
+        F = debug_box_op(s, b, 3, (mi, mi))
+        assert relerr(F, o["F"][I_ci]) < 1e-12, ("F", li)
+        Sci = debug_box_op(s, b, 2, (mi, g4))
+        assert relerr(Sci, o["S"][I_ci][:, perm]) < 1e-12, ("S", li)
+        Hm = debug_box_op(s, b, 4, (g4, mi))
+        assert relerr(Hm, o["H"][perm]) < 1e-12, ("H", li)
+        if info[2] >= 0 or len(boxes) == 1:
+            T = debug_box_op(s, b, 0, (g4, g4))
+            assert relerr(T, o["T"][np.ix_(perm, perm)]) < 1e-12, ("T", li)
+
+
+@pytest.mark.parametrize("nx,ny,p,refine", [(2, 2, 8, None), (4, 4, 8, None),
+                                            (4, 4, 12, None), (2, 2, 8, (0.1, 0.1, 1)),
+                                            (16, 16, 8, None)])
+def test_merge_operators(nx, ny, p, refine):
+    H, s, ot, ops, p, q = _build_pair(nx, ny, p, refine=refine)
+    from paper_1612_02736_amd.hps import debug_boxes, debug_box_nodes, debug_box_op
+    boxes = debug_boxes(s)
+    obox = ot.boxes
+    assert len(obox) == len(boxes)
+    for b, info in enumerate(boxes):
+        if info[0]:
+            continue
+        ob = obox[b]                 # both number boxes in the same pre-order
+        o = ops.box[ob.id]
+        ef, en, m = info[5], info[6], info[7]
+        gi = debug_box_nodes(s, b, 2)
+        nat = debug_box_nodes(s, b, 1)
+        fin = debug_box_nodes(s, b, 0)
+        assert set(gi) == set(ob.gi)
+        pg = {j: i for i, j in enumerate(ob.gi)}
+        ig = np.array([pg[j] for j in gi])
+        X = debug_box_op(s, b, 1, (m, m))
+        assert relerr(X, o["X"][np.ix_(ig, ig)]) < 1e-11, ("X", b)
+        ge_f = ob.ge_fine if ob.ge_fine is not None else ob.ge
+        pn = {j: i for i, j in enumerate(ge_f)}
+        inat = np.array([pn[j] for j in nat])
+        S = debug_box_op(s, b, 2, (m, en))
+        assert relerr(S, o["S"][np.ix_(ig, inat)]) < 1e-11, ("S", b)
+        if info[2] >= 0:
+            pf = {j: i for i, j in enumerate(ob.ge)}
+            ifin = np.array([pf[j] for j in fin])
+            T = debug_box_op(s, b, 0, (ef, ef))
+            assert relerr(T, o["T"][np.ix_(ifin, ifin)]) < 1e-11, ("T", b)
