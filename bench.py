@@ -127,7 +127,7 @@ def main():
     cd = torch.from_numpy(coeffs).to(dev)
     fd = torch.from_numpy(f).to(dev)
     gd = torch.from_numpy(g).to(dev)
-    solver = H.Solver(tree, cd, P, Q)
+    solver = H.Solver(tree, cd, P, Q, keep_fp32=True)
     fm = flop_model(H, solver)
     for _ in range(args.warmup):
         solver.refactor(cd)
@@ -163,13 +163,32 @@ def main():
         solver.solve(f1, g1)
     torch.cuda.synchronize()
     solve1_ms = (time.perf_counter() - s0) * 1e2
+    # mixed precision (FP32 sweeps + FP64 residual refinement) at nrhs = 32
+    stats = {}
+    um = solver.solve(fd, gd, precision=H.HPS_PREC_MIXED, stats=stats)
+    torch.cuda.synchronize()
+    m0 = time.perf_counter()
+    for _ in range(3):
+        um = solver.solve(fd, gd, precision=H.HPS_PREC_MIXED, stats=stats)
+    torch.cuda.synchronize()
+    mixed_ms = (time.perf_counter() - m0) * 1e3 / 3
+    # adjoint (transposed sweeps) at nrhs = 32
+    ub = torch.ones_like(u)
+    solver.solve_adjoint(ub)
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    for _ in range(3):
+        solver.solve_adjoint(ub)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - a0) * 1e3 / 3
     # accuracy against stored oracle values (seed 2 = right-hand side 0)
-    rel_err = None
+    rel_err = rel_err_mixed = None
     ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
     if os.path.exists(ref):
         z = np.load(ref, allow_pickle=False)
-        ug = u[0].cpu().numpy()[z["leaves"]]
-        rel_err = float(np.max(np.abs(ug - z["u"])) / np.max(np.abs(z["u"])))
+        scale = np.max(np.abs(z["u"]))
+        rel_err = float(np.max(np.abs(u[0].cpu().numpy()[z["leaves"]] - z["u"])) / scale)
+        rel_err_mixed = float(np.max(np.abs(um[0].cpu().numpy()[z["leaves"]] - z["u"])) / scale)
     # dominant kernel from the per-launch events of the timed steps
     agg = {}
     for kind, var, ms in prof:
@@ -213,8 +232,15 @@ def main():
         "solves_per_s_fp64_nrhs32": args.nrhs * 1e3 / solve32_ms,
         "solve_ms_fp64_nrhs1": solve1_ms,
         "solves_per_s_fp64_nrhs1": 1e3 / solve1_ms,
+        "solve_ms_mixed_nrhs32": mixed_ms,
+        "solves_per_s_mixed_nrhs32": args.nrhs * 1e3 / mixed_ms,
+        "mixed_refinement_steps": stats.get("iters"),
+        "mixed_last_correction": stats.get("resid"),
+        "adjoint_ms_nrhs32": adj_ms,
+        "adjoint_over_forward": adj_ms / solve32_ms,
         "solve_operator_gb": fm["solve_bytes"] / 1e9,
         "rel_err_vs_oracle": rel_err,
+        "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
     }

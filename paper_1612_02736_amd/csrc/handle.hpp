@@ -53,7 +53,7 @@ struct DevArray {
 };
 
 enum StepKind {
-  S_GEMM, S_GJ_LEAF, S_GJ_MERGE, S_ZDIFF, S_PANEL, S_COLPERM, S_APPLY, S_COPY_F
+  S_GEMM, S_GJ_LEAF, S_GJ_MERGE, S_ZDIFF, S_PANEL, S_COLPERM, S_APPLY, S_COPY_F, S_VECOP
 };
 
 struct Step {
@@ -65,6 +65,7 @@ struct Step {
   int kb = 0;
   int64_t fin0 = 0, nfin = 0;  // APPLY: finalize list range
   int64_t fin_maxm = 0;
+  bool trans = false;         // APPLY: transposed operator
 };
 
 
@@ -98,6 +99,15 @@ struct hps_handle {
   hps::DevArray<hps::ApplyDesc> d_apply;
   hps::DevArray<int32_t> d_finlist;
   std::vector<hps::Step> build_prog, up_prog, down_prog, adj_down_prog, adj_up_prog;
+  std::vector<hps::Step> up_jump_prog, ext_prog;   // refinement-correction solve
+  hps::DevArray<hps::VecOpDesc> d_vecop;
+  // flux-jump residual maps (uniform trees): interior node id, flux index of
+  // the west/south leaf and of the east/north leaf
+  hps::DevArray<int32_t> d_jn, d_fa, d_fb;
+  int64_t n_jump = 0;
+  bool conforming = true;     // no refined interfaces
+  hps::DevArray<double> d_lloc;   // q x p row-major Chebyshev -> Gauss
+  int64_t map_fbar = -1;
   // offsets
   int64_t vec_per_rhs = 0;       // doubles per right-hand side in BUF_VEC
   int64_t ug_off = 0;            // global Gauss vector inside a RHS block

@@ -190,6 +190,7 @@ struct Layout {
   std::vector<int64_t> T, X, S, LD, H, Pup, Pdn, Pups;   // -1 if absent
   std::vector<int64_t> Tn_scr, Tmp_scr, Aie_scr, B_scr, W_scr, ipiv;
   std::vector<int64_t> h, w, hn;                          // vec offsets
+  std::vector<int64_t> Ub, Ubn, wb, hb, hbn;              // adjoint vec offsets
   std::vector<int64_t> map_fin, map_nat, map_gi, map_pi, map_slave;  // imap offsets
   std::vector<int64_t> L_role;                 // ws, per role (5)
   std::vector<int64_t> Dci, T0;                // ws, per (class*5 + role)
@@ -347,7 +348,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
                        std::vector<std::pair<int64_t, std::vector<double>>> &ws_blocks,
                        std::vector<int32_t> &imap, GemmList &gl, std::vector<LeafDesc> &leafd,
                        std::vector<MergeInvDesc> &minv, std::vector<ApplyDesc> &appl,
-                       std::vector<int64_t> &appl_t0, std::vector<int32_t> &finlist) {
+                       std::vector<int64_t> &appl_t0, std::vector<int32_t> &finlist,
+                       std::vector<VecOpDesc> &vops) {
   Plan &pl = H->pl;
   const int p = H->p, q = H->q, mi = H->mi, me = H->me, g4 = H->g4;
   const int nb = (int)pl.boxes.size();
@@ -357,6 +359,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   Lo.Tn_scr.assign(nb, -1); Lo.Tmp_scr.assign(nb, -1); Lo.Aie_scr.assign(nb, -1);
   Lo.B_scr.assign(nb, -1); Lo.W_scr.assign(nb, -1); Lo.ipiv.assign(nb, -1);
   Lo.h.assign(nb, -1); Lo.w.assign(nb, -1); Lo.hn.assign(nb, -1);
+  Lo.Ub.assign(nb, -1); Lo.Ubn.assign(nb, -1); Lo.wb.assign(nb, -1); Lo.hb.assign(nb, -1);
+  Lo.hbn.assign(nb, -1);
   Lo.map_fin.assign(nb, -1); Lo.map_nat.assign(nb, -1); Lo.map_gi.assign(nb, -1);
   Lo.map_pi.assign(nb, -1); Lo.map_slave.assign(nb, -1);
   auto ws_take = [&](int64_t n) { int64_t o = Lo.ws; Lo.ws += (n + 31) / 32 * 32; return o; };
@@ -476,6 +480,18 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     if (!B.leaf) {
       Lo.w[b] = vec_take((int64_t)B.gi.size());
       if (B.coarsened) Lo.hn[b] = vec_take((int64_t)B.nat.size());
+    }
+  }
+  for (int b = 0; b < nb; ++b) {      // adjoint sweeps
+    const Box &B = pl.boxes[b];
+    Lo.Ub[b] = vec_take((int64_t)B.fin.size());
+    Lo.hb[b] = vec_take((int64_t)B.fin.size());
+    if (!B.leaf) {
+      Lo.wb[b] = vec_take((int64_t)B.gi.size());
+      if (B.coarsened) {
+        Lo.Ubn[b] = vec_take((int64_t)B.nat.size());
+        Lo.hbn[b] = vec_take((int64_t)B.nat.size());
+      }
     }
   }
   // --- integer maps ---
@@ -737,8 +753,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         ApplyDesc a = ad(m, m, 0, 1, Lo.X[b], m);
         a.B1 = vref(BUF_VEC, Lo.h[B.beta] + n2, -1, vs);
         a.B2 = vref(BUF_VEC, Lo.h[B.alpha] + n1, -1, vs);
-        a.B3 = vref(BUF_AUX, 0, Lo.map_gi[b], 0);   // flux-jump source; buf patched
-        a.B3.buf = -1;
+        a.B3 = vref(BUF_AUX, 0, Lo.map_gi[b], pl.n_gauss);  // flux-jump source
+        a.B3.buf = -1;                                          // off unless enabled
         a.C = vref(BUF_VEC, Lo.w[b], -1, vs);
         wst.push_back(a);
         if (B.parent < 0) continue;
@@ -812,12 +828,258 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     }
     apply_step(tmp, dn);
   }
+  // transposed applies of the adjoint use the same descriptor layout
+  auto apply_step_t = [&](std::vector<ApplyDesc> &tmp, std::vector<Step> &prg) {
+    if (tmp.empty()) return;
+    apply_step(tmp, prg);
+    prg.back().trans = true;
+  };
+  auto vecop_step = [&](std::vector<VecOpDesc> &tmp, std::vector<Step> &prg) {
+    if (tmp.empty()) return;
+    Step s{S_VECOP};
+    s.d0 = (int64_t)vops.size();
+    s.nd = (int64_t)tmp.size();
+    for (auto &v : tmp) s.maxm = std::max(s.maxm, v.n);
+    vops.insert(vops.end(), tmp.begin(), tmp.end());
+    prg.push_back(s);
+    tmp.clear();
+  };
+  auto vop = [&](int n, VRef dst, VRef a, double ca, VRef b, double cb) {
+    VecOpDesc v{};
+    v.n = n; v.dst = dst; v.a = a; v.b = b; v.ca = ca; v.cb = cb;
+    return v;
+  };
+  // solve with a flux-jump source: the up pass with the B3 operand enabled
+  {
+    H->up_jump_prog.clear();
+    for (const Step &st : H->up_prog) {
+      bool wstep = false;
+      for (int64_t i = st.d0; i < st.d0 + st.nd; ++i)
+        if (appl[i].mode == 1) wstep = true;
+      if (!wstep) { H->up_jump_prog.push_back(st); continue; }
+      std::vector<ApplyDesc> tmp(appl.begin() + st.d0, appl.begin() + st.d0 + st.nd);
+      for (auto &a : tmp) a.B3.buf = BUF_AUX;
+      apply_step(tmp, H->up_jump_prog);
+    }
+  }
+  // exterior Chebyshev values u_c(I_ce) = L u_ge alone (FP64 recompute)
+  {
+    H->ext_prog.clear();
+    std::vector<ApplyDesc> tmp;
+    for (int i = 0; i < nleaf; ++i) {
+      const int li = pl.leaves[i];
+      ApplyDesc e = ad(me, g4, 0, 0, Lo.L_role[pl.boxes[li].role], me);
+      e.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], vs);
+      e.C = vref(BUF_IN2, int64_t(i) * p * p, H->ice_map, ustride);
+      tmp.push_back(e);
+    }
+    apply_step(tmp, H->ext_prog);
+  }
+  // adjoint, reverse of the downward pass (children before parents):
+  // inputs ubar (BUF_IN0), outputs fbar (BUF_IN1) and gbar (BUF_IN2)
+  {
+    auto &P = H->adj_down_prog;
+    P.clear();
+    std::vector<ApplyDesc> t1, t2;
+    for (int i = 0; i < nleaf; ++i) {
+      const int li = pl.leaves[i];
+      const int role = pl.boxes[li].role;
+      ApplyDesc a = ad(g4, me, 0, 0, Lo.L_role[role], me);      // L^T ubar(I_ce)
+      a.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ice_map, ustride);
+      a.C = vref(BUF_VEC, Lo.Ub[li], -1, vs);
+      t1.push_back(a);
+      ApplyDesc b = ad(g4, mi, 0, 0, Lo.LD[li], mi);            // + S_ci^T ubar(I_ci)
+      b.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ici_map, ustride);
+      b.D = vref(BUF_VEC, Lo.Ub[li], -1, vs);
+      b.beta = 1.0;
+      b.C = vref(BUF_VEC, Lo.Ub[li], -1, vs);
+      t2.push_back(b);
+      ApplyDesc c = ad(mi, mi, 0, 0, Lo.LD[li] + int64_t(g4) * mi, mi);   // F^T ubar(I_ci)
+      c.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ici_map, ustride);
+      c.C = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
+      t2.push_back(c);
+    }
+    apply_step_t(t1, P);
+    apply_step_t(t2, P);
+    for (int h = 1; h <= pl.max_height; ++h) {
+      std::vector<int> lev;
+      for (int b = 0; b < nb; ++b)
+        if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
+      if (lev.empty()) continue;
+      std::vector<VecOpDesc> v1;
+      std::vector<ApplyDesc> a2, a3;
+      for (int b : lev) {
+        const Box &B = pl.boxes[b];
+        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+        const int m = (int)B.gi.size();
+        const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+        const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
+        // wbar = ubar at the interior edge, summed over both children
+        v1.push_back(vop(m, vref(BUF_VEC, Lo.wb[b], -1, vs), vref(BUF_VEC, Lo.Ub[B.alpha] + n1, -1, vs),
+                         1.0, vref(BUF_VEC, Lo.Ub[B.beta] + n2, -1, vs), 1.0));
+        for (int part = 0; part < 2; ++part) {
+          const int M = part == 0 ? n1 : n2;
+          if (M == 0) continue;
+          ApplyDesc a = ad(M, m, 0, 0, Lo.S[b] + (part == 0 ? 0 : int64_t(n1) * m), m);
+          a.B1 = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.D = vref(BUF_VEC, part == 0 ? Lo.Ub[B.alpha] : Lo.Ub[B.beta], -1, vs);
+          a.beta = 1.0;
+          if (B.coarsened) a.C = vref(BUF_VEC, Lo.Ubn[b] + (part == 0 ? 0 : n1), -1, vs);
+          else a.C = vref(BUF_VEC, Lo.Ub[b], Lo.map_pi[b] + (part == 0 ? 0 : n1), vs);
+          a2.push_back(a);
+        }
+        if (B.coarsened) {
+          ApplyDesc c = ad(ef, en, 0, 0, Lo.Pup[b], en);        // P_up^T
+          c.B1 = vref(BUF_VEC, Lo.Ubn[b], -1, vs);
+          c.C = vref(BUF_VEC, Lo.Ub[b], -1, vs);
+          a3.push_back(c);
+        }
+      }
+      vecop_step(v1, P);
+      apply_step_t(a2, P);
+      apply_step_t(a3, P);
+    }
+    // fbar at the canonical boundary nodes from the roots' boundary slots
+    std::vector<int32_t> fmap(pl.bdry.size());
+    {
+      std::unordered_map<int64_t, int64_t> where;
+      for (int b = 0; b < nb; ++b) {
+        const Box &B = pl.boxes[b];
+        if (B.parent >= 0) continue;
+        for (size_t k = 0; k < B.fin.size(); ++k) where[B.fin[k]] = Lo.Ub[b] + (int64_t)k;
+      }
+      for (size_t k = 0; k < pl.bdry.size(); ++k) fmap[k] = (int32_t)where[pl.bdry[k]];
+    }
+    H->map_fbar = imap_put(fmap);
+    std::vector<VecOpDesc> fv{vop((int)pl.bdry.size(), vref(BUF_IN1, 0, -1, H->n_bdry),
+                                  vref(BUF_VEC, 0, H->map_fbar, vs), 1.0, vref(-1, 0, -1, 0), 0.0)};
+    fv[0].b.buf = -1;
+    vecop_step(fv, P);
+  }
+  // adjoint, reverse of the upward pass (parents before children)
+  {
+    auto &P = H->adj_up_prog;
+    P.clear();
+    for (int h = pl.max_height; h >= 1; --h) {
+      std::vector<int> lev;
+      for (int b = 0; b < nb; ++b)
+        if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
+      if (lev.empty()) continue;
+      std::vector<ApplyDesc> u1, u2, u3, u4;
+      std::vector<VecOpDesc> u5;
+      for (int b : lev) {
+        const Box &B = pl.boxes[b];
+        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+        const int m = (int)B.gi.size();
+        const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+        const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
+        const bool root = B.parent < 0;
+        // hbar in natural order: P_down^T hbar, or hbar through the permutation
+        auto hnat = [&](int off) {
+          if (B.coarsened) return vref(BUF_VEC, Lo.hbn[b] + off, -1, vs);
+          return vref(BUF_VEC, Lo.hb[b], Lo.map_pi[b] + off, vs);
+        };
+        if (!root && B.coarsened) {
+          ApplyDesc a = ad(en, ef, 0, 0, Lo.Pdn[b], ef);
+          a.B1 = vref(BUF_VEC, Lo.hb[b], -1, vs);
+          a.C = vref(BUF_VEC, Lo.hbn[b], -1, vs);
+          u1.push_back(a);
+        }
+        if (!root && n1 > 0) {                       // wbar += T13a^T hbar_1
+          ApplyDesc a = ad(m, n1, 0, 0, Lo.T[B.alpha] + int64_t(n1) * ea, ea);
+          a.B1 = hnat(0);
+          a.D = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.beta = 1.0;
+          a.C = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          u2.push_back(a);
+        }
+        if (!root && n2 > 0) {                       // wbar += T23b^T hbar_2
+          ApplyDesc a = ad(m, n2, 0, 0, Lo.T[B.beta] + int64_t(n2) * eb, eb);
+          a.B1 = hnat(n1);
+          a.D = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.beta = 1.0;
+          a.C = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          u3.push_back(a);
+        }
+        for (int side = 0; side < 2; ++side) {       // d = X^T wbar into h3a (-), h3b (+)
+          ApplyDesc a = ad(m, m, 0, 0, Lo.X[b], m);
+          a.B1 = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.alpha = side == 0 ? -1.0 : 1.0;
+          a.C = side == 0 ? vref(BUF_VEC, Lo.hb[B.alpha] + n1, -1, vs)
+                          : vref(BUF_VEC, Lo.hb[B.beta] + n2, -1, vs);
+          u4.push_back(a);
+        }
+        for (int side = 0; side < 2; ++side) {       // kept parts pass through
+          const int n = side == 0 ? n1 : n2;
+          if (n == 0) continue;
+          VecOpDesc v = vop(n, vref(BUF_VEC, side == 0 ? Lo.hb[B.alpha] : Lo.hb[B.beta], -1, vs),
+                            hnat(side == 0 ? 0 : n1), 1.0, vref(-1, 0, -1, 0), 0.0);
+          v.b.buf = -1;
+          if (root) v.a.buf = -1;                    // the root's hbar is zero
+          u5.push_back(v);
+        }
+      }
+      apply_step_t(u1, P);
+      apply_step_t(u2, P);
+      apply_step_t(u3, P);
+      apply_step_t(u4, P);
+      vecop_step(u5, P);
+    }
+    std::vector<ApplyDesc> g;
+    for (int i = 0; i < nleaf; ++i) {                // gbar += H^T hbar
+      const int li = pl.leaves[i];
+      ApplyDesc a = ad(mi, g4, 0, 0, Lo.H[li], g4);
+      a.B1 = vref(BUF_VEC, Lo.hb[li], -1, vs);
+      a.D = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
+      a.beta = 1.0;
+      a.C = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
+      g.push_back(a);
+    }
+    if (pl.max_height == 0) {                        // a single leaf: hbar = 0
+      g.clear();
+    }
+    apply_step_t(g, P);
+  }
+  // flux-jump maps of the refinement residual (conforming trees only)
+  {
+    bool conf = true;
+    for (const Box &B : pl.boxes) if (B.coarsened) conf = false;
+    H->conforming = conf;
+    std::vector<int32_t> jn, fa, fb;
+    if (conf) {
+      // owner (leaf index, natural position) of each node on each side
+      std::vector<int64_t> own_a(pl.n_gauss, -1), own_b(pl.n_gauss, -1);
+      for (int i = 0; i < nleaf; ++i) {
+        const Box &B = pl.boxes[pl.leaves[i]];
+        for (int k = 0; k < g4; ++k) {
+          const int64_t j = B.nat[k];
+          const int side = k / q;
+          // west/south leaf sees the node on its E or N side: alpha side
+          if (side == 1 || side == 2) own_a[j] = int64_t(i) * g4 + k;
+          else own_b[j] = int64_t(i) * g4 + k;
+        }
+      }
+      for (int64_t j = 0; j < pl.n_gauss; ++j)
+        if (own_a[j] >= 0 && own_b[j] >= 0) {
+          jn.push_back((int32_t)j);
+          fa.push_back((int32_t)own_a[j]);
+          fb.push_back((int32_t)own_b[j]);
+        }
+    }
+    H->n_jump = (int64_t)jn.size();
+    if (H->d_jn.upload(jn) != hipSuccess || H->d_fa.upload(fa) != hipSuccess ||
+        H->d_fb.upload(fb) != hipSuccess)
+      return fail(HPS_EHIP, "upload of residual maps");
+    std::vector<double> xc = cheb_points(p), xg = legendre_roots(q);
+    std::vector<double> Lloc = interp_matrix(xc, xg);
+    if (H->d_lloc.upload(Lloc) != hipSuccess) return fail(HPS_EHIP, "upload of L_loc");
+  }
   H->part_per_rhs = part_off;
   H->off_T = Lo.T; H->off_X = Lo.X; H->off_S = Lo.S; H->off_LD = Lo.LD; H->off_H = Lo.H;
   return HPS_OK;
 }
 
-static Bases make_bases(hps_handle *H) {
+Bases make_bases(hps_handle *H) {
   Bases b{};
   b.d[BUF_WS] = H->ws.p;
   b.d[BUF_SCR] = H->scr.p;
@@ -837,8 +1099,8 @@ static hipEvent_t prof_event(hps_handle *H) {
   return H->prof_pool[H->prof_used++];
 }
 
-static int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, int prec,
-                    hipStream_t st) {
+int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, int prec,
+             hipStream_t st) {
   for (const Step &s : prog) {
     hipError_t e = hipSuccess;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -871,10 +1133,13 @@ static int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int 
         break;
       case S_APPLY:
         e = launch_apply(prec, H->d_apply.p + s.d0, H->d_apply_t0.p + s.d0, (int)s.nd, s.ntiles,
-                         bs, nrhs, st);
+                         bs, nrhs, st, s.trans);
         if (e == hipSuccess && s.nfin > 0)
           e = launch_apply_finalize(H->d_apply.p, H->d_finlist.p + s.fin0, (int)s.nfin,
                                     s.fin_maxm, bs, nrhs, st);
+        break;
+      case S_VECOP:
+        e = launch_vecop(H->d_vecop.p + s.d0, (int)s.nd, s.maxm, bs, nrhs, st);
         break;
       default:
         break;
@@ -910,7 +1175,8 @@ size_t hps_build_workspace_size(const hps_tree *tree, int p, int q) {
   std::vector<ApplyDesc> ap;
   std::vector<int64_t> at0;
   std::vector<int32_t> fl;
-  if (plan_handle(&H, Lo, wi, blocks, imap, gl, ld, mv, ap, at0, fl)) return 0;
+  std::vector<VecOpDesc> vo;
+  if (plan_handle(&H, Lo, wi, blocks, imap, gl, ld, mv, ap, at0, fl, vo)) return 0;
   return size_t(Lo.ws) * sizeof(double);
 }
 
@@ -943,7 +1209,9 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   std::vector<ApplyDesc> appl;
   std::vector<int64_t> appl_t0;
   std::vector<int32_t> finlist;
-  rc = plan_handle(H.get(), Lo, aux_init, blocks, imap, gl, leafd, minv, appl, appl_t0, finlist);
+  std::vector<VecOpDesc> vops;
+  rc = plan_handle(H.get(), Lo, aux_init, blocks, imap, gl, leafd, minv, appl, appl_t0, finlist,
+                   vops);
   if (rc) return rc;
   H->solve_elems = (size_t)Lo.solve_ws;
   H->scr_build = Lo.scr + 64;
@@ -965,6 +1233,7 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   HIPCHK(H->d_apply.upload(appl));
   HIPCHK(H->d_apply_t0.upload(appl_t0));
   HIPCHK(H->d_finlist.upload(finlist));
+  HIPCHK(H->d_vecop.upload(vops));
   // keep the coefficients (residuals of mixed-precision solves use them)
   const size_t ncoef = size_t(H->nleaf) * 6 * p * p;
   HIPCHK(H->coef.alloc(ncoef));
@@ -1033,7 +1302,7 @@ void hps_handle_free(hps_handle *h) { delete h; }
 // ---------------------------------------------------------------------------
 // solve
 // ---------------------------------------------------------------------------
-static int ensure_solve_buffers(hps_handle *H, int nrhs) {
+int ensure_solve_buffers(hps_handle *H, int nrhs) {
   const size_t need_vec = size_t(H->vec_per_rhs) * nrhs;
   if (H->vec.n < need_vec) HIPCHK(H->vec.alloc(need_vec));
   const size_t need_part = size_t(H->part_per_rhs) * nrhs + 64;
@@ -1057,13 +1326,8 @@ int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, do
   bs.d[BUF_IN1] = (void *)g;
   bs.d[BUF_IN2] = (void *)u;
   bs.d[BUF_AUX] = (void *)jump;
-  if (jump) {
-    // the w-steps carry an optional B3 source; enable it by switching the
-    // buffer id on a private copy of the program
-    rc = solve_ext_run_up_with_jump(H, bs, nrhs, prec, st);
-  } else {
-    rc = run_prog(H, H->up_prog, bs, nrhs, prec, st);
-  }
+  // with a flux-jump source the w-steps read it as their third operand
+  rc = run_prog(H, jump ? H->up_jump_prog : H->up_prog, bs, nrhs, prec, st);
   if (rc) return rc;
   HIPCHK(launch_copy_map(bs, vref(BUF_VEC, H->ug_off, H->map_bdry, H->vec_per_rhs),
                          vref(BUF_IN0, 0, -1, H->n_bdry), H->n_bdry, nrhs, st));

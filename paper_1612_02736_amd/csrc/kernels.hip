@@ -576,7 +576,7 @@ __device__ __forceinline__ double vload(const Bases &bs, const VRef &v, int64_t 
   return ((const double *)bs.d[v.buf])[v.off + idx + r * v.stride];
 }
 
-template <typename TA, typename TC_, int NR>
+template <typename TA, typename TC_, int NR, bool TRANS>
 __global__ __launch_bounds__(256) void apply_kernel(
     const ApplyDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
     int ndesc, int64_t ntiles, Bases bs, int nrhs) {
@@ -607,9 +607,11 @@ __global__ __launch_bounds__(256) void apply_kernel(
       if (rg < nrhs) {
         if (d.mode == 0) {
           v = k < d.K1 ? vload(bs, d.B1, k, rg) : vload(bs, d.B2, k - d.K1, rg);
-        } else {
+        } else if (d.mode == 1) {
           v = vload(bs, d.B1, k, rg) - vload(bs, d.B2, k, rg);
           if (d.B3.buf >= 0) v += vload(bs, d.B3, k, rg);
+        } else {
+          v = vload(bs, d.B1, k, rg) + vload(bs, d.B2, k, rg);
         }
       }
       Bsh[kk][r] = TC_(v);
@@ -617,12 +619,24 @@ __global__ __launch_bounds__(256) void apply_kernel(
     __syncthreads();
     const int q4 = (kn + 3) >> 2, ka = wid * q4, kz = min(kn, ka + q4);
     if (row < d.M) {
-      const TA *Ap = A + row + int64_t(kc) * lda;
+      if (!TRANS) {
+        // output row `row` of A (column-major): stride lda along k
+        const TA *Ap = A + row + int64_t(kc) * lda;
 #pragma unroll 8
-      for (int kk = ka; kk < kz; ++kk) {
-        const TC_ av = TC_(Ap[int64_t(kk) * lda]);
+        for (int kk = ka; kk < kz; ++kk) {
+          const TC_ av = TC_(Ap[int64_t(kk) * lda]);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = fma(av, Bsh[kk][r], acc[r]);
+          for (int r = 0; r < NR; ++r) acc[r] = fma(av, Bsh[kk][r], acc[r]);
+        }
+      } else {
+        // output = column `row` of A: contiguous along k
+        const TA *Ap = A + int64_t(row) * lda + kc;
+#pragma unroll 8
+        for (int kk = ka; kk < kz; ++kk) {
+          const TC_ av = TC_(Ap[kk]);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) acc[r] = fma(av, Bsh[kk][r], acc[r]);
+        }
       }
     }
     __syncthreads();
@@ -679,6 +693,22 @@ __global__ __launch_bounds__(256) void copy_map_kernel(Bases bs, VRef dst, VRef 
     const double v = vload(bs, src, i, r);
     const int64_t di = dst.map >= 0 ? bs.imap[dst.map + i] : i;
     ((double *)bs.d[dst.buf])[dst.off + di + r * dst.stride] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void vecop_kernel(const VecOpDesc *__restrict__ descs,
+                                                    int nd, Bases bs, int nrhs) {
+  const VecOpDesc &d = descs[blockIdx.y];
+  const int64_t tot = int64_t(d.n) * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(e / d.n);
+    const int64_t k = e - int64_t(r) * d.n;
+    double v = 0.0;
+    if (d.a.buf >= 0) v += d.ca * vload(bs, d.a, k, r);
+    if (d.b.buf >= 0) v += d.cb * vload(bs, d.b, k, r);
+    const int64_t di = d.dst.map >= 0 ? bs.imap[d.dst.map + k] : k;
+    ((double *)bs.d[d.dst.buf])[d.dst.off + di + r * d.dst.stride] = v;
   }
 }
 
@@ -815,36 +845,43 @@ hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const 
   return hipGetLastError();
 }
 
-template <typename TA, typename TC_>
+template <typename TA, typename TC_, bool TRANS>
 static void launch_apply_t(const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
                            int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st) {
   const int64_t nblk = (ntiles + 7) / 8 * 8;
   if (nrhs >= 8) {
     dim3 g(unsigned(nblk), unsigned((nrhs + 7) / 8));
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 8>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 8, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
                        ntiles, bs, nrhs);
   } else if (nrhs >= 4) {
     dim3 g(unsigned(nblk), unsigned((nrhs + 3) / 4));
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 4>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 4, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
                        ntiles, bs, nrhs);
   } else if (nrhs >= 2) {
     dim3 g(unsigned(nblk), unsigned((nrhs + 1) / 2));
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 2>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 2, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
                        ntiles, bs, nrhs);
   } else {
     dim3 g(unsigned(nblk), 1);
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 1>), g, dim3(256), 0, st, descs, tile0s, ndesc,
+    hipLaunchKernelGGL((apply_kernel<TA, TC_, 1, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
                        ntiles, bs, nrhs);
   }
 }
 
 hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
-                        int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st) {
+                        int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st, bool trans) {
   if (ntiles <= 0) return hipSuccess;
-  if (prec == 0)
-    launch_apply_t<double, double>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
-  else
-    launch_apply_t<float, float>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+  if (trans) {
+    if (prec == 0)
+      launch_apply_t<double, double, true>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+    else
+      launch_apply_t<float, float, true>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+  } else {
+    if (prec == 0)
+      launch_apply_t<double, double, false>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+    else
+      launch_apply_t<float, float, false>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+  }
   return hipGetLastError();
 }
 
@@ -861,6 +898,14 @@ hipError_t launch_copy_map(const Bases &bs, const VRef &dst, const VRef &src, in
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_map_kernel, dim3(grid_1d(n * nrhs)), dim3(256), 0, st, bs, dst, src,
                      n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_vecop(const VecOpDesc *descs, int nd, int64_t maxn, const Bases &bs, int nrhs,
+                        hipStream_t st) {
+  if (nd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vecop_kernel, dim3(grid_1d(maxn * nrhs, 64), nd), dim3(256), 0, st, descs,
+                     nd, bs, nrhs);
   return hipGetLastError();
 }
 

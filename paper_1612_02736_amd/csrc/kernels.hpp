@@ -27,11 +27,14 @@ hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
 hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
                              int32_t *ipiv, int32_t *src, hipStream_t st);
 hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
-                        int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st);
+                        int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st,
+                        bool trans = false);
 hipError_t launch_apply_finalize(const ApplyDesc *descs, const int32_t *list, int nlist,
                                  int64_t maxm, const Bases &bs, int nrhs, hipStream_t st);
 hipError_t launch_copy_map(const Bases &bs, const VRef &dst, const VRef &src, int64_t n,
                            int nrhs, hipStream_t st);
+hipError_t launch_vecop(const VecOpDesc *descs, int nd, int64_t maxn, const Bases &bs, int nrhs,
+                        hipStream_t st);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t st);
 

@@ -1,0 +1,226 @@
+// Kernels of the solve-stage extensions: the FP64 residual of the global
+// collocation system (for iterative refinement of FP32 solves), vector
+// updates and reductions, and the coefficient gradient of the adjoint.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels_ext.hpp"
+
+namespace hps {
+
+// One workgroup per (leaf, right-hand side).  Residual of the collocated PDE
+// at interior nodes, r = g - A u (Sec. 3.2, same A as the build), and the
+// leaf's boundary fluxes D_ge,c u (Sec. 3.4) in side order S, E, N, W.
+template <int P>
+__global__ __launch_bounds__(256) void residual_kernel(
+    const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
+    const double *__restrict__ uc, const double *__restrict__ g, double *__restrict__ r1,
+    double *__restrict__ flux, const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
+    const double *__restrict__ Lloc_g, int q) {
+  constexpr int PP = P * P, PI = P - 2, MI = PI * PI;
+  __shared__ double u[PP], dx[PP], dy[PP], Dh[PP], Dh2[PP], cf[6][PP], Lloc[P * P];
+  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int64_t nl = nleaf;
+  const LeafDesc &d = leafd[leaf];
+  const double sx = d.sx, sy = d.sy;
+  for (int i = tid; i < PP; i += 256) {
+    u[i] = uc[(int64_t(r) * nl + leaf) * PP + i];
+    Dh[i] = Dh_g[i];
+    Dh2[i] = Dh2_g[i];
+  }
+  for (int i = tid; i < q * P; i += 256) Lloc[i] = Lloc_g[i];
+  for (int i = tid; i < 6 * PP; i += 256) cf[i / PP][i % PP] = coef[int64_t(leaf) * 6 * PP + i];
+  __syncthreads();
+  // reference-coordinate first derivatives on the whole grid
+  for (int t = tid; t < PP; t += 256) {
+    const int iy = t / P, ix = t - iy * P;
+    double sxv = 0.0, syv = 0.0;
+    for (int j = 0; j < P; ++j) {
+      sxv += Dh[ix * P + j] * u[iy * P + j];
+      syv += Dh[iy * P + j] * u[j * P + ix];
+    }
+    dx[t] = sxv;
+    dy[t] = syv;
+  }
+  __syncthreads();
+  for (int a = tid; a < MI; a += 256) {
+    const int y = a / PI, iy = y + 1, ix = a - y * PI + 1, t = iy * P + ix;
+    double uxx = 0.0, uyy = 0.0, uxy = 0.0;
+    for (int j = 0; j < P; ++j) {
+      uxx += Dh2[ix * P + j] * u[iy * P + j];
+      uyy += Dh2[iy * P + j] * u[j * P + ix];
+      uxy += Dh[iy * P + j] * dx[j * P + ix];
+    }
+    const double Au = -cf[0][t] * sx * sx * uxx - 2.0 * cf[1][t] * sx * sy * uxy -
+                      cf[2][t] * sy * sy * uyy + cf[3][t] * sx * dx[t] + cf[4][t] * sy * dy[t] +
+                      cf[5][t] * u[t];
+    const int64_t o = (int64_t(r) * nl + leaf) * MI + a;
+    r1[o] = g[o] - Au;
+  }
+  for (int k = tid; k < 4 * q; k += 256) {
+    const int side = k / q, kk = k - side * q;
+    double v = 0.0;
+    for (int j = 0; j < P; ++j) {
+      const double l = Lloc[kk * P + j];
+      if (side == 0) v += l * sy * dy[0 * P + j];
+      else if (side == 1) v += l * sx * dx[j * P + (P - 1)];
+      else if (side == 2) v += l * sy * dy[(P - 1) * P + j];
+      else v += l * sx * dx[j * P + 0];
+    }
+    flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
+  }
+}
+
+// jump(node) = flux of the east/north leaf - flux of the west/south leaf
+__global__ __launch_bounds__(256) void jump_kernel(const int32_t *__restrict__ jn,
+                                                   const int32_t *__restrict__ fa,
+                                                   const int32_t *__restrict__ fb, int64_t n,
+                                                   const double *__restrict__ flux,
+                                                   int64_t flux_stride, double *__restrict__ jump,
+                                                   int64_t jump_stride, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(e / n);
+    const int64_t i = e - int64_t(r) * n;
+    jump[r * jump_stride + jn[i]] = flux[r * flux_stride + fb[i]] - flux[r * flux_stride + fa[i]];
+  }
+}
+
+// x(k, r) += y(k, r); y(k, r) = x(k, r)  (strided blocks of n per RHS)
+__global__ __launch_bounds__(256) void accumulate_kernel(double *__restrict__ x, int64_t xs,
+                                                         double *__restrict__ y, int64_t ys,
+                                                         int64_t n, int nrhs, int copy_back) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(e / n);
+    const int64_t k = e - int64_t(r) * n;
+    const double v = x[r * xs + k] + y[r * ys + k];
+    x[r * xs + k] = v;
+    if (copy_back) y[r * ys + k] = v;
+  }
+}
+
+// out[0] = max |a|, out[1] = max |b| over n entries.  Non-negative doubles
+// order like their bit patterns, so each workgroup's maximum is merged with
+// an unsigned 64-bit atomic max; out must hold zeros on entry.
+__global__ __launch_bounds__(256) void maxabs2_kernel(const double *__restrict__ a,
+                                                      const double *__restrict__ b, int64_t n,
+                                                      unsigned long long *__restrict__ out) {
+  __shared__ double sa[256], sb[256];
+  double ma = 0.0, mb = 0.0;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    ma = fmax(ma, fabs(a[e]));
+    mb = fmax(mb, fabs(b[e]));
+  }
+  sa[threadIdx.x] = ma;
+  sb[threadIdx.x] = mb;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] = fmax(sa[threadIdx.x], sa[threadIdx.x + s]);
+      sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(sa[0]));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(sb[0]));
+  }
+}
+
+__global__ void zero2_kernel(unsigned long long *out) {
+  if (threadIdx.x < 2) out[threadIdx.x] = 0ull;
+}
+
+// cbar = -gbar * u at interior nodes, 0 at exterior nodes
+__global__ __launch_bounds__(256) void cbar_kernel(const double *__restrict__ u,
+                                                   const double *__restrict__ gbar,
+                                                   double *__restrict__ cbar, int p, int64_t nl,
+                                                   int nrhs) {
+  const int pp = p * p, pi = p - 2;
+  const int64_t tot = int64_t(nrhs) * nl * pp;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t lr = e / pp;
+    const int t = int(e - lr * pp), iy = t / p, ix = t - iy * p;
+    double v = 0.0;
+    if (iy > 0 && iy < p - 1 && ix > 0 && ix < p - 1)
+      v = -gbar[lr * pi * pi + (iy - 1) * pi + (ix - 1)] * u[e];
+    cbar[e] = v;
+  }
+}
+
+static inline unsigned grid1(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return unsigned(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double *coef,
+                           const double *uc, const double *g, double *r1, double *flux,
+                           const double *Dh, const double *Dh2, const double *Lloc, int q,
+                           int nrhs, hipStream_t st) {
+  dim3 grid(nleaf, nrhs);
+  switch (p) {
+    case 16:
+      hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
+                         r1, flux, Dh, Dh2, Lloc, q);
+      break;
+    case 12:
+      hipLaunchKernelGGL(residual_kernel<12>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
+                         r1, flux, Dh, Dh2, Lloc, q);
+      break;
+    case 10:
+      hipLaunchKernelGGL(residual_kernel<10>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
+                         r1, flux, Dh, Dh2, Lloc, q);
+      break;
+    case 8:
+      hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
+                         r1, flux, Dh, Dh2, Lloc, q);
+      break;
+    case 6:
+      hipLaunchKernelGGL(residual_kernel<6>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
+                         r1, flux, Dh, Dh2, Lloc, q);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb, int64_t n,
+                       const double *flux, int64_t flux_stride, double *jump, int64_t jump_stride,
+                       int nrhs, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jump_kernel, dim3(grid1(n * nrhs)), dim3(256), 0, st, jn, fa, fb, n, flux,
+                     flux_stride, jump, jump_stride, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double *x, int64_t xs, double *y, int64_t ys, int64_t n, int nrhs,
+                             int copy_back, hipStream_t st) {
+  hipLaunchKernelGGL(accumulate_kernel, dim3(grid1(n * nrhs)), dim3(256), 0, st, x, xs, y, ys, n,
+                     nrhs, copy_back);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs2(const double *a, const double *b, int64_t n, double *out,
+                          hipStream_t st) {
+  unsigned long long *o = reinterpret_cast<unsigned long long *>(out);
+  hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(64), 0, st, o);
+  hipLaunchKernelGGL(maxabs2_kernel, dim3(grid1(n / 4 + 1)), dim3(256), 0, st, a, b, n, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_cbar(const double *u, const double *gbar, double *cbar, int p, int64_t nl,
+                       int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(cbar_kernel, dim3(grid1(int64_t(nrhs) * nl * p * p)), dim3(256), 0, st, u,
+                     gbar, cbar, p, nl, nrhs);
+  return hipGetLastError();
+}
+
+}  // namespace hps

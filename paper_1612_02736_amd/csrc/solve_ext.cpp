@@ -1,27 +1,135 @@
+// Solve-stage extensions on top of the planned programs:
+//  * mixed precision: FP32 sweeps (FP32 copies of the FP64-built operators)
+//    corrected by iterative refinement against the FP64 residual of the
+//    global collocation system;
+//  * the adjoint: transposed sweeps of Algorithm 2 and the gradient with
+//    respect to the zeroth-order coefficient.
 #include "solve_ext.hpp"
 
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "kernels.hpp"
+#include "kernels_ext.hpp"
+
 namespace hps {
-struct SolveExt {};
+
+struct SolveExt {
+  DevArray<double> xug, jump, r1, flux, duc, zf, red;
+  int cap = 0;
+};
+
 void solve_ext_free(SolveExt *p) { delete p; }
+
 }  // namespace hps
 
-int solve_ext_init(hps_handle *H) { (void)H; return HPS_OK; }
+using namespace hps;
 
-int solve_ext_run_up_with_jump(hps_handle *, const hps::Bases &, int, int, hipStream_t) {
-  return hps::fail(HPS_EINVAL, "flux-jump sources are not available");
+int solve_ext_init(hps_handle *H) {
+  H->ext.reset(new SolveExt);
+  return HPS_OK;
 }
 
-int solve_ext_mixed(hps_handle *, const double *, const double *, int, double *,
-                    const hps_solve_opts *, hipStream_t) {
-  return hps::fail(HPS_EINVAL, "mixed precision is not available");
+static int ext_buffers(hps_handle *H, int nrhs) {
+  SolveExt &E = *H->ext;
+  if (E.cap >= nrhs) return HPS_OK;
+  const size_t N = size_t(H->pl.n_gauss), nl = size_t(H->nleaf);
+  HIPCHK(E.xug.alloc(N * nrhs));
+  HIPCHK(E.jump.alloc(N * nrhs));
+  HIPCHK(E.r1.alloc(nl * H->mi * nrhs));
+  HIPCHK(E.flux.alloc(nl * H->g4 * nrhs));
+  HIPCHK(E.duc.alloc(nl * H->p * H->p * nrhs));
+  HIPCHK(E.zf.alloc(size_t(H->n_bdry) * nrhs));
+  HIPCHK(hipMemset(E.zf.p, 0, sizeof(double) * H->n_bdry * nrhs));
+  HIPCHK(E.jump.p ? hipMemset(E.jump.p, 0, sizeof(double) * N * nrhs) : hipSuccess);
+  HIPCHK(E.red.alloc(2));
+  E.cap = nrhs;
+  return HPS_OK;
 }
 
-extern "C" int hps_solve_adjoint(hps_handle *, const double *, int, double *, double *,
-                                 const hps_solve_opts *) {
-  return hps::fail(HPS_EINVAL, "adjoint is not available");
+// u_c(I_ce) = L u_ge in FP64 from the global Gauss vector held in BUF_VEC
+static int recompute_exterior(hps_handle *H, double *u, int nrhs, hipStream_t st) {
+  Bases bs = make_bases(H);
+  bs.d[BUF_IN2] = u;
+  return run_prog(H, H->ext_prog, bs, nrhs, 0, st);
 }
 
-extern "C" int hps_coeff_grad_c(hps_handle *, const double *, const double *, int, double *,
-                                void *) {
-  return hps::fail(HPS_EINVAL, "adjoint is not available");
+int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, double *u,
+                    const hps_solve_opts *opts, hipStream_t st) {
+  if (!H->has_fp32) return fail(HPS_EINVAL, "mixed precision needs a build with keep_fp32");
+  if (!H->conforming)
+    return fail(HPS_EINVAL, "mixed precision is available on trees without refined interfaces");
+  int rc = ext_buffers(H, nrhs);
+  if (rc) return rc;
+  SolveExt &E = *H->ext;
+  const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 6;
+  const double tol = opts && opts->ir_tol > 0.0 ? opts->ir_tol : 1e-13;
+  const int64_t N = H->pl.n_gauss, vs = H->vec_per_rhs;
+  const int64_t ucn = int64_t(H->nleaf) * H->p * H->p;
+  // first FP32 pass on the original data
+  rc = hps_solve_pass(H, f, g, nrhs, u, 1, nullptr, st);
+  if (rc) return rc;
+  double *vug = H->vec.p + H->ug_off;
+  HIPCHK(launch_fill(E.xug.p, 0.0, N * nrhs, st));
+  HIPCHK(launch_accumulate(E.xug.p, N, vug, vs, N, nrhs, 0, st));
+  rc = recompute_exterior(H, u, nrhs, st);
+  if (rc) return rc;
+  int it = 0;
+  double ratio = 1.0;
+  for (; it < max_iter; ++it) {
+    HIPCHK(launch_residual(H->p, H->d_leaf.p, H->nleaf, H->coef.p, u, g, E.r1.p, E.flux.p,
+                           H->aux.p + H->Dh_off, H->aux.p + H->Dh2_off, H->d_lloc.p, H->q, nrhs,
+                           st));
+    HIPCHK(launch_jump(H->d_jn.p, H->d_fa.p, H->d_fb.p, H->n_jump, E.flux.p,
+                       int64_t(H->nleaf) * H->g4, E.jump.p, N, nrhs, st));
+    rc = hps_solve_pass(H, E.zf.p, E.r1.p, nrhs, E.duc.p, 1, E.jump.p, st);
+    if (rc) return rc;
+    HIPCHK(launch_accumulate(E.xug.p, N, vug, vs, N, nrhs, 1, st));
+    HIPCHK(launch_accumulate(u, ucn, E.duc.p, ucn, ucn, nrhs, 0, st));
+    rc = recompute_exterior(H, u, nrhs, st);
+    if (rc) return rc;
+    HIPCHK(launch_maxabs2(E.duc.p, u, ucn * nrhs, E.red.p, st));
+    double m[2];
+    HIPCHK(hipMemcpyAsync(m, E.red.p, sizeof(m), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ratio = m[1] > 0.0 ? m[0] / m[1] : 0.0;
+    if (!(ratio == ratio)) return fail(HPS_ENONFINITE, "non-finite refinement correction");
+    if (ratio <= tol) { ++it; break; }
+  }
+  if (opts && opts->iters_out) *opts->iters_out = it;
+  if (opts && opts->resid_out) *opts->resid_out = ratio;
+  if (ratio > 1e-8)
+    return fail(HPS_ENOCONV, "iterative refinement stalled at max|du|/max|u| = " +
+                                 std::to_string(ratio));
+  return HPS_OK;
+}
+
+extern "C" int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs, double *fbar,
+                                 double *gbar, const hps_solve_opts *opts) {
+  if (!h || !ubar || !fbar || !gbar) return fail(HPS_EINVAL, "NULL argument");
+  if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  int rc = ensure_solve_buffers(h, nrhs);
+  if (rc) return rc;
+  Bases bs = make_bases(h);
+  bs.d[BUF_IN0] = (void *)ubar;
+  bs.d[BUF_IN1] = fbar;
+  bs.d[BUF_IN2] = gbar;
+  rc = run_prog(h, h->adj_down_prog, bs, nrhs, 0, st);
+  if (rc) return rc;
+  rc = run_prog(h, h->adj_up_prog, bs, nrhs, 0, st);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
+}
+
+extern "C" int hps_coeff_grad_c(hps_handle *h, const double *u, const double *gbar, int nrhs,
+                                double *cbar, void *stream) {
+  if (!h || !u || !gbar || !cbar) return fail(HPS_EINVAL, "NULL argument");
+  if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_cbar(u, gbar, cbar, h->p, h->nleaf, nrhs, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
 }

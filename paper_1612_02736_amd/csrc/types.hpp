@@ -71,8 +71,9 @@ struct VRef {
 };
 
 // C(map(i), r) = alpha * sum_k A(i,k) B(k,r) + beta * D(i,r)
-// B rows k < K1 come from B1, k >= K1 from B2 (mode 0); in mode 1
-// B(k) = B1(k) - B2(k) (+ B3(k) if present), K = K1.
+// (or A(k,i) for the transposed launch).  B rows k < K1 come from B1,
+// k >= K1 from B2 (mode 0); in mode 1 B(k) = B1(k) - B2(k) (+ B3(k) if
+// present); in mode 2 B(k) = B1(k) + B2(k); K = K1 in modes 1 and 2.
 struct ApplyDesc {
   int32_t M, K1, K2, mode;
   int32_t ksl, rb;      // k-slices and 64-row blocks
@@ -82,6 +83,13 @@ struct ApplyDesc {
   VRef B1, B2, B3, C, D;
   double alpha, beta;
   int64_t part;         // split-K partials start at BUF_SCR[part * nrhs]
+};
+
+// dst(k, r) = ca * a(k, r) + cb * b(k, r) for k < n (absent operands are 0).
+struct VecOpDesc {
+  int32_t n, pad;
+  VRef dst, a, b;
+  double ca, cb;
 };
 
 }  // namespace hps

@@ -136,3 +136,21 @@ def test_singular_and_nonfinite_inputs_are_reported():
     with pytest.raises(H.HPSError) as e:
         H.Solver(t, to_dev(c), p)
     assert e.value.code == -4
+
+
+def test_full_size_workload2_against_stored_oracle():
+    """64 x 64 leaves, p = 16, seeded Fourier solution (seed 2): FP64 and
+    mixed-precision solves against oracle values written by
+    tests/golden/make_oracle_refs.py (every 64th leaf)."""
+    import os
+    H = _lib()
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden",
+                               "oracle_varcoeff_64x64_p16_seed2.npz"), allow_pickle=False)
+    p, q = 16, 15
+    t = H.Tree(0, 1, 0, 1, 64, 64)
+    coeffs, f, g, _ = lib_inputs(t, p, q, W.varcoeff, W.FourierSolution(2))
+    s = H.Solver(t, to_dev(coeffs), p, q, keep_fp32=True)
+    u = s.solve(to_dev(f[None]), to_dev(g[None]))[0].cpu().numpy()
+    assert relerr(u[ref["leaves"]], ref["u"]) <= TOL
+    um = s.solve(to_dev(f[None]), to_dev(g[None]), precision=H.HPS_PREC_MIXED)[0].cpu().numpy()
+    assert relerr(um[ref["leaves"]], ref["u"]) <= 1e-10
