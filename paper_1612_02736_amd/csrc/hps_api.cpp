@@ -304,12 +304,13 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
     prog.push_back(s);
   }
   if (big.empty()) return;
+  const int NBp = panel_nb(bigmax);
   const int64_t d0 = (int64_t)minv.size();
   minv.insert(minv.end(), big.begin(), big.end());
   Step z{S_ZDIFF};
   z.d0 = d0; z.nd = (int64_t)big.size(); z.maxm = bigmax;
   prog.push_back(z);
-  for (int kb = 0; kb < bigmax; kb += kPanelNB) {
+  for (int kb = 0; kb < bigmax; kb += NBp) {
     Step s{S_PANEL};
     s.d0 = d0; s.nd = (int64_t)big.size(); s.kb = kb; s.maxm = bigmax;
     prog.push_back(s);
@@ -317,7 +318,7 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
     for (const MergeInvDesc &d : big) {
       const int m = d.m;
       if (kb >= m) continue;
-      const int nbv = std::min(kPanelNB, m - kb), ke = kb + nbv;
+      const int nbv = std::min(NBp, m - kb), ke = kb + nbv;
       const int rows[3][2] = {{0, kb}, {kb, ke}, {ke, m}};
       const int cols[2][2] = {{0, kb}, {ke, m}};
       for (int ri = 0; ri < 3; ++ri)
@@ -327,7 +328,7 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
           GemmDesc g{};
           g.M = r1 - r0; g.N = c1 - c0; g.K = nbv;
           g.A = ref(BUF_WS, d.X + r0 + int64_t(kb) * m, m);
-          g.B = ref(BUF_SCR, d.W + int64_t(c0) * kPanelNB, kPanelNB);
+          g.B = ref(BUF_SCR, d.W + int64_t(c0) * NBp, NBp);
           g.C = ref(BUF_WS, d.X + r0 + int64_t(c0) * m, m);
           g.D = (ri == 1) ? noref() : ref(BUF_WS, d.X + r0 + int64_t(c0) * m, m);
           g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = (ri == 1) ? 0.0 : 1.0;
@@ -464,7 +465,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     if (B.leaf) continue;
     const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
     if (gj_merge_class(m) < 0) {
-      Lo.W_scr[b] = scr_take(std::max<int64_t>(int64_t(kPanelNB) * m, int64_t(m) * m));
+      Lo.W_scr[b] = scr_take(std::max<int64_t>(int64_t(kPanelNBMax) * m, int64_t(m) * m));
       Lo.ipiv[b] = Lo.ipiv_n;
       Lo.ipiv_n += m;
     }
@@ -734,7 +735,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       const int li = pl.leaves[i];
       ApplyDesc a = ad(g4, mi, 0, 0, Lo.H[li], g4);
       a.B1 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
-      a.C = vref(BUF_VEC, Lo.h[li], -1, vs);
+      a.C = vref(BUF_VEC, Lo.h[li], -1, kInterleaved);
       tmp.push_back(a);
     }
     apply_step(tmp, up);
@@ -751,11 +752,11 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
         const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
         ApplyDesc a = ad(m, m, 0, 1, Lo.X[b], m);
-        a.B1 = vref(BUF_VEC, Lo.h[B.beta] + n2, -1, vs);
-        a.B2 = vref(BUF_VEC, Lo.h[B.alpha] + n1, -1, vs);
-        a.B3 = vref(BUF_AUX, 0, Lo.map_gi[b], pl.n_gauss);  // flux-jump source
+        a.B1 = vref(BUF_VEC, Lo.h[B.beta] + n2, -1, kInterleaved);
+        a.B2 = vref(BUF_VEC, Lo.h[B.alpha] + n1, -1, kInterleaved);
+        a.B3 = vref(BUF_AUX, 0, Lo.map_gi[b], kInterleaved);  // flux-jump source
         a.B3.buf = -1;                                          // off unless enabled
-        a.C = vref(BUF_VEC, Lo.w[b], -1, vs);
+        a.C = vref(BUF_VEC, Lo.w[b], -1, kInterleaved);
         wst.push_back(a);
         if (B.parent < 0) continue;
         for (int part = 0; part < 2; ++part) {
@@ -764,17 +765,17 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
           const int64_t Tsrc = part == 0 ? Lo.T[B.alpha] + int64_t(n1) * ea
                                          : Lo.T[B.beta] + int64_t(n2) * eb;
           ApplyDesc c = ad(M, m, 0, 0, Tsrc, part == 0 ? ea : eb);
-          c.B1 = vref(BUF_VEC, Lo.w[b], -1, vs);
-          c.D = vref(BUF_VEC, part == 0 ? Lo.h[B.alpha] : Lo.h[B.beta], -1, vs);
+          c.B1 = vref(BUF_VEC, Lo.w[b], -1, kInterleaved);
+          c.D = vref(BUF_VEC, part == 0 ? Lo.h[B.alpha] : Lo.h[B.beta], -1, kInterleaved);
           c.beta = 1.0;
-          if (B.coarsened) c.C = vref(BUF_VEC, Lo.hn[b] + (part == 0 ? 0 : n1), -1, vs);
-          else c.C = vref(BUF_VEC, Lo.h[b], Lo.map_pi[b] + (part == 0 ? 0 : n1), vs);
+          if (B.coarsened) c.C = vref(BUF_VEC, Lo.hn[b] + (part == 0 ? 0 : n1), -1, kInterleaved);
+          else c.C = vref(BUF_VEC, Lo.h[b], Lo.map_pi[b] + (part == 0 ? 0 : n1), kInterleaved);
           hst.push_back(c);
         }
         if (B.coarsened) {
           ApplyDesc c = ad(ef, en, 0, 0, Lo.Pdn[b], ef);
-          c.B1 = vref(BUF_VEC, Lo.hn[b], -1, vs);
-          c.C = vref(BUF_VEC, Lo.h[b], -1, vs);
+          c.B1 = vref(BUF_VEC, Lo.hn[b], -1, kInterleaved);
+          c.C = vref(BUF_VEC, Lo.h[b], -1, kInterleaved);
           cst.push_back(c);
         }
       }
@@ -799,15 +800,15 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
         if (B.coarsened && !B.slave_rows.empty()) {
           ApplyDesc a = ad((int)B.slave_rows.size(), ef, 0, 0, Lo.Pups[b], (int)B.slave_rows.size());
-          a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[b], vs);
-          a.C = vref(BUF_VEC, H->ug_off, Lo.map_slave[b], vs);
+          a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[b], kInterleaved);
+          a.C = vref(BUF_VEC, H->ug_off, Lo.map_slave[b], kInterleaved);
           sl.push_back(a);
         }
         ApplyDesc a = ad(m, en, 0, 0, Lo.S[b], m);
-        a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_nat[b], vs);
-        a.D = vref(BUF_VEC, Lo.w[b], -1, vs);
+        a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_nat[b], kInterleaved);
+        a.D = vref(BUF_VEC, Lo.w[b], -1, kInterleaved);
         a.beta = 1.0;
-        a.C = vref(BUF_VEC, H->ug_off, Lo.map_gi[b], vs);
+        a.C = vref(BUF_VEC, H->ug_off, Lo.map_gi[b], kInterleaved);
         ug.push_back(a);
       }
       apply_step(sl, dn);
@@ -817,12 +818,12 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       const int li = pl.leaves[i];
       const int role = pl.boxes[li].role;
       ApplyDesc a = ad(mi, g4, mi, 0, Lo.LD[li], mi);
-      a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], vs);
+      a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], kInterleaved);
       a.B2 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
       a.C = vref(BUF_IN2, int64_t(i) * p * p, H->ici_map, ustride);
       tmp.push_back(a);
       ApplyDesc e = ad(me, g4, 0, 0, Lo.L_role[role], me);
-      e.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], vs);
+      e.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], kInterleaved);
       e.C = vref(BUF_IN2, int64_t(i) * p * p, H->ice_map, ustride);
       tmp.push_back(e);
     }
@@ -869,7 +870,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     for (int i = 0; i < nleaf; ++i) {
       const int li = pl.leaves[i];
       ApplyDesc e = ad(me, g4, 0, 0, Lo.L_role[pl.boxes[li].role], me);
-      e.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], vs);
+      e.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], kInterleaved);
       e.C = vref(BUF_IN2, int64_t(i) * p * p, H->ice_map, ustride);
       tmp.push_back(e);
     }
@@ -886,13 +887,13 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       const int role = pl.boxes[li].role;
       ApplyDesc a = ad(g4, me, 0, 0, Lo.L_role[role], me);      // L^T ubar(I_ce)
       a.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ice_map, ustride);
-      a.C = vref(BUF_VEC, Lo.Ub[li], -1, vs);
+      a.C = vref(BUF_VEC, Lo.Ub[li], -1, kInterleaved);
       t1.push_back(a);
       ApplyDesc b = ad(g4, mi, 0, 0, Lo.LD[li], mi);            // + S_ci^T ubar(I_ci)
       b.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ici_map, ustride);
-      b.D = vref(BUF_VEC, Lo.Ub[li], -1, vs);
+      b.D = vref(BUF_VEC, Lo.Ub[li], -1, kInterleaved);
       b.beta = 1.0;
-      b.C = vref(BUF_VEC, Lo.Ub[li], -1, vs);
+      b.C = vref(BUF_VEC, Lo.Ub[li], -1, kInterleaved);
       t2.push_back(b);
       ApplyDesc c = ad(mi, mi, 0, 0, Lo.LD[li] + int64_t(g4) * mi, mi);   // F^T ubar(I_ci)
       c.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ici_map, ustride);
@@ -915,23 +916,23 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
         const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
         // wbar = ubar at the interior edge, summed over both children
-        v1.push_back(vop(m, vref(BUF_VEC, Lo.wb[b], -1, vs), vref(BUF_VEC, Lo.Ub[B.alpha] + n1, -1, vs),
-                         1.0, vref(BUF_VEC, Lo.Ub[B.beta] + n2, -1, vs), 1.0));
+        v1.push_back(vop(m, vref(BUF_VEC, Lo.wb[b], -1, kInterleaved), vref(BUF_VEC, Lo.Ub[B.alpha] + n1, -1, kInterleaved),
+                         1.0, vref(BUF_VEC, Lo.Ub[B.beta] + n2, -1, kInterleaved), 1.0));
         for (int part = 0; part < 2; ++part) {
           const int M = part == 0 ? n1 : n2;
           if (M == 0) continue;
           ApplyDesc a = ad(M, m, 0, 0, Lo.S[b] + (part == 0 ? 0 : int64_t(n1) * m), m);
-          a.B1 = vref(BUF_VEC, Lo.wb[b], -1, vs);
-          a.D = vref(BUF_VEC, part == 0 ? Lo.Ub[B.alpha] : Lo.Ub[B.beta], -1, vs);
+          a.B1 = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
+          a.D = vref(BUF_VEC, part == 0 ? Lo.Ub[B.alpha] : Lo.Ub[B.beta], -1, kInterleaved);
           a.beta = 1.0;
-          if (B.coarsened) a.C = vref(BUF_VEC, Lo.Ubn[b] + (part == 0 ? 0 : n1), -1, vs);
-          else a.C = vref(BUF_VEC, Lo.Ub[b], Lo.map_pi[b] + (part == 0 ? 0 : n1), vs);
+          if (B.coarsened) a.C = vref(BUF_VEC, Lo.Ubn[b] + (part == 0 ? 0 : n1), -1, kInterleaved);
+          else a.C = vref(BUF_VEC, Lo.Ub[b], Lo.map_pi[b] + (part == 0 ? 0 : n1), kInterleaved);
           a2.push_back(a);
         }
         if (B.coarsened) {
           ApplyDesc c = ad(ef, en, 0, 0, Lo.Pup[b], en);        // P_up^T
-          c.B1 = vref(BUF_VEC, Lo.Ubn[b], -1, vs);
-          c.C = vref(BUF_VEC, Lo.Ub[b], -1, vs);
+          c.B1 = vref(BUF_VEC, Lo.Ubn[b], -1, kInterleaved);
+          c.C = vref(BUF_VEC, Lo.Ub[b], -1, kInterleaved);
           a3.push_back(c);
         }
       }
@@ -952,7 +953,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     }
     H->map_fbar = imap_put(fmap);
     std::vector<VecOpDesc> fv{vop((int)pl.bdry.size(), vref(BUF_IN1, 0, -1, H->n_bdry),
-                                  vref(BUF_VEC, 0, H->map_fbar, vs), 1.0, vref(-1, 0, -1, 0), 0.0)};
+                                  vref(BUF_VEC, 0, H->map_fbar, kInterleaved), 1.0, vref(-1, 0, -1, 0), 0.0)};
     fv[0].b.buf = -1;
     vecop_step(fv, P);
   }
@@ -976,43 +977,43 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         const bool root = B.parent < 0;
         // hbar in natural order: P_down^T hbar, or hbar through the permutation
         auto hnat = [&](int off) {
-          if (B.coarsened) return vref(BUF_VEC, Lo.hbn[b] + off, -1, vs);
-          return vref(BUF_VEC, Lo.hb[b], Lo.map_pi[b] + off, vs);
+          if (B.coarsened) return vref(BUF_VEC, Lo.hbn[b] + off, -1, kInterleaved);
+          return vref(BUF_VEC, Lo.hb[b], Lo.map_pi[b] + off, kInterleaved);
         };
         if (!root && B.coarsened) {
           ApplyDesc a = ad(en, ef, 0, 0, Lo.Pdn[b], ef);
-          a.B1 = vref(BUF_VEC, Lo.hb[b], -1, vs);
-          a.C = vref(BUF_VEC, Lo.hbn[b], -1, vs);
+          a.B1 = vref(BUF_VEC, Lo.hb[b], -1, kInterleaved);
+          a.C = vref(BUF_VEC, Lo.hbn[b], -1, kInterleaved);
           u1.push_back(a);
         }
         if (!root && n1 > 0) {                       // wbar += T13a^T hbar_1
           ApplyDesc a = ad(m, n1, 0, 0, Lo.T[B.alpha] + int64_t(n1) * ea, ea);
           a.B1 = hnat(0);
-          a.D = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.D = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
           a.beta = 1.0;
-          a.C = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.C = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
           u2.push_back(a);
         }
         if (!root && n2 > 0) {                       // wbar += T23b^T hbar_2
           ApplyDesc a = ad(m, n2, 0, 0, Lo.T[B.beta] + int64_t(n2) * eb, eb);
           a.B1 = hnat(n1);
-          a.D = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.D = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
           a.beta = 1.0;
-          a.C = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.C = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
           u3.push_back(a);
         }
         for (int side = 0; side < 2; ++side) {       // d = X^T wbar into h3a (-), h3b (+)
           ApplyDesc a = ad(m, m, 0, 0, Lo.X[b], m);
-          a.B1 = vref(BUF_VEC, Lo.wb[b], -1, vs);
+          a.B1 = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
           a.alpha = side == 0 ? -1.0 : 1.0;
-          a.C = side == 0 ? vref(BUF_VEC, Lo.hb[B.alpha] + n1, -1, vs)
-                          : vref(BUF_VEC, Lo.hb[B.beta] + n2, -1, vs);
+          a.C = side == 0 ? vref(BUF_VEC, Lo.hb[B.alpha] + n1, -1, kInterleaved)
+                          : vref(BUF_VEC, Lo.hb[B.beta] + n2, -1, kInterleaved);
           u4.push_back(a);
         }
         for (int side = 0; side < 2; ++side) {       // kept parts pass through
           const int n = side == 0 ? n1 : n2;
           if (n == 0) continue;
-          VecOpDesc v = vop(n, vref(BUF_VEC, side == 0 ? Lo.hb[B.alpha] : Lo.hb[B.beta], -1, vs),
+          VecOpDesc v = vop(n, vref(BUF_VEC, side == 0 ? Lo.hb[B.alpha] : Lo.hb[B.beta], -1, kInterleaved),
                             hnat(side == 0 ? 0 : n1), 1.0, vref(-1, 0, -1, 0), 0.0);
           v.b.buf = -1;
           if (root) v.a.buf = -1;                    // the root's hbar is zero
@@ -1029,7 +1030,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     for (int i = 0; i < nleaf; ++i) {                // gbar += H^T hbar
       const int li = pl.leaves[i];
       ApplyDesc a = ad(mi, g4, 0, 0, Lo.H[li], g4);
-      a.B1 = vref(BUF_VEC, Lo.hb[li], -1, vs);
+      a.B1 = vref(BUF_VEC, Lo.hb[li], -1, kInterleaved);
       a.D = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
       a.beta = 1.0;
       a.C = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
@@ -1122,6 +1123,7 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
         break;
       case S_ZDIFF:
         e = launch_zdiff(H->d_minv.p + s.d0, (int)s.nd, s.maxm, bs, st);
+        if (e == hipSuccess) e = launch_gj_ginit(H->d_minv.p + s.d0, (int)s.nd, s.maxm, H->ipiv.p, st);
         break;
       case S_PANEL:
         e = launch_gj_panel(H->d_minv.p + s.d0, (int)s.nd, s.kb, s.maxm, bs, H->ipiv.p,
@@ -1329,7 +1331,7 @@ int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, do
   // with a flux-jump source the w-steps read it as their third operand
   rc = run_prog(H, jump ? H->up_jump_prog : H->up_prog, bs, nrhs, prec, st);
   if (rc) return rc;
-  HIPCHK(launch_copy_map(bs, vref(BUF_VEC, H->ug_off, H->map_bdry, H->vec_per_rhs),
+  HIPCHK(launch_copy_map(bs, vref(BUF_VEC, H->ug_off, H->map_bdry, kInterleaved),
                          vref(BUF_IN0, 0, -1, H->n_bdry), H->n_bdry, nrhs, st));
   return run_prog(H, H->down_prog, bs, nrhs, prec, st);
 }
@@ -1348,10 +1350,10 @@ extern "C" int hps_solve(hps_handle *h, const double *f, const double *g, int nr
   }
   if (rc) return rc;
   if (opts && opts->u_gauss) {
-    for (int r = 0; r < nrhs; ++r)
-      HIPCHK(hipMemcpyAsync(opts->u_gauss + int64_t(r) * h->pl.n_gauss,
-                            h->vec.p + int64_t(r) * h->vec_per_rhs + h->ug_off,
-                            sizeof(double) * h->pl.n_gauss, hipMemcpyDeviceToDevice, st));
+    Bases bs = make_bases(h);
+    bs.d[BUF_IN0] = opts->u_gauss;
+    HIPCHK(launch_copy_map(bs, vref(BUF_IN0, 0, -1, h->pl.n_gauss),
+                           vref(BUF_VEC, h->ug_off, -1, kInterleaved), h->pl.n_gauss, nrhs, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   return HPS_OK;
@@ -1391,7 +1393,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   HIPCHK(H.ws.alloc(size_t(nn) * (2 * batch + 1)));
   HIPCHK(hipMemcpyAsync(H.ws.p, A, sizeof(double) * nn * batch, hipMemcpyDeviceToDevice, st));
   HIPCHK(launch_fill(H.ws.p + nn * batch, 0.0, nn, st));
-  const int64_t wsz = std::max<int64_t>(int64_t(kPanelNB) * n, nn);
+  const int64_t wsz = std::max<int64_t>(int64_t(kPanelNBMax) * n, nn);
   HIPCHK(H.scr.alloc(size_t(wsz) * batch + 64));
   HIPCHK(H.ipiv.alloc(size_t(n) * batch));
   HIPCHK(H.psrc.alloc(size_t(n) * batch));

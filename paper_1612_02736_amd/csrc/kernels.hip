@@ -44,11 +44,51 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Pivot search keys: |x| (non-negative, so its bit pattern orders like the
+// value) with the low 12 mantissa bits replaced by 4095 - row.  The largest
+// key is the largest |x| (to 2^-40 relative) and, among those, the lowest row;
+// rows that are not candidates carry key 0.  NaN keys exceed every finite key,
+// so a NaN pivot is found and reported.
+__device__ __forceinline__ unsigned long long pivot_key(double x, int row) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(x));
+  return (b & ~0xFFFull) | (unsigned long long)(4095 - row);
+}
+__device__ __forceinline__ int key_row(unsigned long long k) { return 4095 - int(k & 0xFFFull); }
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, false);
+  return (unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32);
+}
+
+// Maximum of a 64-bit key over the 64 lanes, returned wave-uniform: DPP
+// butterflies inside each 16-lane row, then the four row results by readlane.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  unsigned long long o;
+  o = dpp_u64<0xB1>(v);  v = o > v ? o : v;     // quad_perm [1,0,3,2]
+  o = dpp_u64<0x4E>(v);  v = o > v ? o : v;     // quad_perm [2,3,0,1]
+  o = dpp_u64<0x141>(v); v = o > v ? o : v;     // row_half_mirror
+  o = dpp_u64<0x140>(v); v = o > v ? o : v;     // row_mirror
+  unsigned long long m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = __builtin_amdgcn_readlane(int(unsigned(v)), 16 * r);
+    const unsigned hi = __builtin_amdgcn_readlane(int(unsigned(v >> 32)), 16 * r);
+    const unsigned long long x = (unsigned long long)lo | ((unsigned long long)hi << 32);
+    m = x > m ? x : m;
+  }
+  return m;
+}
+
 // ---------------------------------------------------------------------------
 // Grouped FP64 GEMM (MFMA)
 // ---------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBM = 64, GBN = 64, GBK = 32;
 
+// 64 x 64 output tile per workgroup (4 wavefronts, each 32 x 32 = 2 x 2 MFMA
+// tiles), K in steps of 32: the next A/B tiles are fetched into registers
+// while the MFMAs run on the current tiles in LDS.
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     const GemmDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
     int ndesc, int64_t ntiles, Bases bs) {
@@ -65,26 +105,44 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
   const int lda = d.A.ld, ldb = d.B.ld;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid & 1, wn = wid >> 1;
+  // per-thread load coordinates
+  const int ar = tid & 63, ak = tid >> 6;        // A: rows ar, k = ak + 4 s
+  const int bk = tid & 31, bc = tid >> 5;        // B: k = bk, cols bc + 8 s
+  const bool arow_ok = row0 + ar < M;
+  const double *Ap = A + (row0 + ar);
   dbl4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-
+  double ra[8], rb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int gk = k0 + ak + 4 * s;
+      ra[s] = (arow_ok && gk < K) ? Ap[int64_t(gk) * lda] : 0.0;
+    }
+    const int gk = k0 + bk;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int gc = col0 + bc + 8 * s;
+      rb[s] = (gk < K && gc < N) ? B[gk + int64_t(gc) * ldb] : 0.0;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) As[ak + 4 * s][ar] = ra[s];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) Bs[bk][bc + 8 * s] = rb[s];
+  };
+  if (K > 0) {
+    fetch(0);
+    stash();
+  }
+  __syncthreads();
   for (int k0 = 0; k0 < K; k0 += GBK) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int r = tid & 63, kk = (tid >> 6) + 4 * s;
-      const int gr = row0 + r, gk = k0 + kk;
-      As[kk][r] = (gr < M && gk < K) ? A[gr + int64_t(gk) * lda] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = tid & 15, c = (tid >> 4) + 16 * s;
-      const int gk = k0 + kk, gc = col0 + c;
-      Bs[kk][c] = (gk < K && gc < N) ? B[gk + int64_t(gc) * ldb] : 0.0;
-    }
-    __syncthreads();
+    const bool more = k0 + GBK < K;
+    if (more) fetch(k0 + GBK);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       const int ka = kk + (lane >> 4), li = lane & 15;
@@ -98,6 +156,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
   }
   double *C = (double *)bs.d[d.C.buf] + d.C.off;
   const double *D = d.D.buf >= 0 ? (const double *)bs.d[d.D.buf] + d.D.off : nullptr;
@@ -142,11 +204,46 @@ template <int TR, int TC, int RA, int CB>
 struct GJShared {
   double colbuf[2][TR * RA];
   double rowbuf[TC * CB];
+  unsigned long long cand[2][2];
   int pivrow[TR * RA];
   int stepof[TR * RA];
-  unsigned char used[TR * RA];
   int info;
 };
+
+// Pivot candidate of column c among the unused rows owned by the TR threads
+// of column owner tc = c mod TC (a contiguous run of TR threads that spans
+// one or two wavefronts).  Each of those wavefronts reduces its lanes and
+// lane 0 stores the result in slot 0 (first wavefront of the run) or 1.
+template <int TR, int TC, int RA, int CB>
+__device__ __forceinline__ void gj_candidate(const double (&a)[RA][CB], const unsigned umask,
+                                             const int n, const int c, const int tr,
+                                             const int tc, GJShared<TR, TC, RA, CB> &sh,
+                                             const int par) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int cb = c / TC, ctc = c - cb * TC;
+  const int lo = ctc * TR, hi = lo + TR - 1;          // owner thread range
+  const int wlo = lo >> 6, whi = hi >> 6;
+  if (wid < wlo || wid > whi) return;                 // uniform per wavefront
+  unsigned long long key = 0;
+  if (tc == ctc) {
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      const int row = tr + TR * i;
+      if (row < n && !((umask >> i) & 1u)) {
+        double x = 0.0;
+#pragma unroll
+        for (int b = 0; b < CB; ++b) if (b == cb) x = a[i][b];
+        const unsigned long long k2 = pivot_key(x, row);
+        key = k2 > key ? k2 : key;
+      }
+    }
+  }
+  key = wave_max_u64(key);
+  if (lane == 0) {
+    sh.cand[par][wid == wlo ? 0 : 1] = key;
+    if (wlo == whi) sh.cand[par][1] = 0;
+  }
+}
 
 // Thread (tr, tc) owns rows tr + TR*i and columns tc + TC*b.  On exit the
 // registers hold the swept matrix M with M[r_k][k'] = inv[k][r_k'] where r_k
@@ -155,8 +252,8 @@ template <int TR, int TC, int RA, int CB>
 __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
                                         const int tr, const int tc,
                                         GJShared<TR, TC, RA, CB> &sh) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  for (int i = tid; i < TR * RA; i += blockDim.x) sh.used[i] = 0;
+  const int tid = threadIdx.x;
+  unsigned umask = 0u;                                // used rows among my RA rows
   if (tid == 0) sh.info = 0;
   if (tc == 0) {
 #pragma unroll
@@ -165,28 +262,17 @@ __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
       if (row < n) sh.colbuf[0][row] = a[i][0];
     }
   }
+  gj_candidate<TR, TC, RA, CB>(a, umask, n, 0, tr, tc, sh, 0);
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const double *cb = sh.colbuf[k & 1];
-    double best = -3.0;
-    int bi = 0x7fffffff;
-    for (int i = lane; i < n; i += 64) {
-      if (!sh.used[i]) {
-        const double x = cb[i];
-        const double v = (x != x) ? -1.0 : fabs(x);
-        if (v > best) { best = v; bi = i; }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const int r = __builtin_amdgcn_readfirstlane(bi);
+    const int par = k & 1;
+    const double *cb = sh.colbuf[par];
+    const unsigned long long k0 = sh.cand[par][0], k1c = sh.cand[par][1];
+    const int r = __builtin_amdgcn_readfirstlane(key_row(k0 > k1c ? k0 : k1c));
     const double piv = cb[r];
     const int ir = r / TR;
-    if (tr == r - ir * TR) {
+    const bool rown = (tr == r - ir * TR);
+    if (rown) {
 #pragma unroll
       for (int i = 0; i < RA; ++i)
         if (i == ir) {
@@ -196,6 +282,7 @@ __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
             if (col < n) sh.rowbuf[col] = a[i][b];
           }
         }
+      umask |= 1u << ir;
     }
     const bool ok = (piv != 0.0) && isfinite(piv);
     if (tid == 0) {
@@ -231,7 +318,7 @@ __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
           }
         }
     }
-    if (tr == r - ir * TR) {
+    if (rown) {
 #pragma unroll
       for (int i = 0; i < RA; ++i)
         if (i == ir) {
@@ -239,7 +326,6 @@ __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
           for (int b = 0; b < CB; ++b) a[i][b] = (kown && b == kb) ? ip : s[b];
         }
     }
-    if (tid == 0) sh.used[r] = 1;
     if (k + 1 < n) {
       const int k1 = k + 1, kb1 = k1 / TC;
       if (tc == k1 - kb1 * TC) {
@@ -253,6 +339,7 @@ __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
             }
           }
       }
+      gj_candidate<TR, TC, RA, CB>(a, umask, n, k1, tr, tc, sh, k1 & 1);
     }
     __syncthreads();
   }
@@ -382,30 +469,31 @@ __global__ __launch_bounds__(256) void zdiff_kernel(const MergeInvDesc *__restri
 }
 
 // One workgroup per matrix: unblocked Gauss-Jordan on the NB columns
-// [kb, kb+NB) held in registers (row t + 512 i owned by thread t), pivot rows
-// chosen among rows >= k, rows swapped across the whole matrix, then the old
-// pivot rows outside the panel copied to W (NB x m, ld NB) for the update.
-template <int NB, int RPT>
-__global__ __launch_bounds__(512) void gj_panel_kernel(
+// [kb, kb+NB) held in registers (row t + NT i owned by thread t), pivot rows
+// chosen among rows >= k, rows interchanged across the whole matrix, then the
+// old pivot rows outside the panel copied to W (NB x m, ld NB) for the
+// rank-NB update.  The inverse of the accumulated row permutation is kept in
+// G (G[k] <-> G[r] per interchange); the final inverse is X(:, G[i]) = Y(:, i).
+template <int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_panel_kernel(
     const MergeInvDesc *__restrict__ descs, int nd, int kb, Bases bs,
-    int32_t *__restrict__ ipiv_all, int32_t *__restrict__ info) {
-  __shared__ double wbest[8];
-  __shared__ int wbi[8];
+    int32_t *__restrict__ g_all, int32_t *__restrict__ info) {
+  constexpr int NW = NT / 64;
+  __shared__ unsigned long long wkey[NW];
   __shared__ double prow[NB];
   __shared__ double srow[NB];
-  __shared__ int s_r;
   __shared__ int s_piv[NB];
   const MergeInvDesc &d = descs[blockIdx.x];
   const int n = d.m;
   if (kb >= n) return;
   const int nbv = min(NB, n - kb);
   double *A = (double *)bs.d[BUF_WS] + d.X;
-  int32_t *ipiv = ipiv_all + d.ipiv;
+  int32_t *G = g_all + d.ipiv;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double pan[RPT][NB];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int row = tid + 512 * i;
+    const int row = tid + NT * i;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       pan[i][c] = (row < n && c < nbv) ? A[row + int64_t(kb + c) * n] : 0.0;
@@ -413,44 +501,35 @@ __global__ __launch_bounds__(512) void gj_panel_kernel(
   int first_bad = 0;
   for (int c = 0; c < nbv; ++c) {
     const int k = kb + c;
-    double best = -3.0;
-    int bi = 0x7fffffff;
+    unsigned long long key = 0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + 512 * i;
+      const int row = tid + NT * i;
       if (row >= k && row < n) {
         double x = 0.0;
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) if (cc == c) x = pan[i][cc];
-        const double v = (x != x) ? -1.0 : fabs(x);
-        if (v > best || (v == best && row < bi)) { best = v; bi = row; }
+        const unsigned long long k2 = pivot_key(x, row);
+        key = k2 > key ? k2 : key;
       }
     }
-#pragma unroll
-    for (int off = 32; off; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { wbest[wid] = best; wbi[wid] = bi; }
+    key = wave_max_u64(key);
+    if (lane == 0) wkey[wid] = key;
     __syncthreads();
-    if (wid == 0) {
-      double b2 = lane < 8 ? wbest[lane] : -3.0;
-      int i2 = lane < 8 ? wbi[lane] : 0x7fffffff;
+    unsigned long long best = 0;
 #pragma unroll
-      for (int off = 32; off; off >>= 1) {
-        const double ob = __shfl_xor(b2, off);
-        const int oi = __shfl_xor(i2, off);
-        if (ob > b2 || (ob == b2 && oi < i2)) { b2 = ob; i2 = oi; }
-      }
-      if (lane == 0) { s_r = i2; s_piv[c] = i2; ipiv[k] = i2; }
+    for (int w = 0; w < NW; ++w) best = wkey[w] > best ? wkey[w] : best;
+    const int r = __builtin_amdgcn_readfirstlane(key_row(best));
+    if (tid == 0) {
+      s_piv[c] = r;
+      const int32_t t0 = G[k];
+      G[k] = G[r];
+      G[r] = t0;
     }
-    __syncthreads();
-    const int r = s_r;
-    // exchange rows k and r inside the panel; prow = new row k
+    // rows r and k travel through LDS; prow = the new row k
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + 512 * i;
+      const int row = tid + NT * i;
       if (row == r) {
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) prow[cc] = pan[i][cc];
@@ -463,7 +542,7 @@ __global__ __launch_bounds__(512) void gj_panel_kernel(
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + 512 * i;
+      const int row = tid + NT * i;
       if (row == r && r != k) {
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) pan[i][cc] = srow[cc];
@@ -481,7 +560,7 @@ __global__ __launch_bounds__(512) void gj_panel_kernel(
     const double ip = ok ? 1.0 / piv : 0.0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + 512 * i;
+      const int row = tid + NT * i;
       double f = 0.0;
 #pragma unroll
       for (int cc = 0; cc < NB; ++cc) if (cc == c) f = pan[i][cc];
@@ -494,67 +573,58 @@ __global__ __launch_bounds__(512) void gj_panel_kernel(
           pan[i][cc] = (cc == c) ? -f * ip : fma(-f, prow[cc] * ip, pan[i][cc]);
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // write the panel back
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int row = tid + 512 * i;
+    const int row = tid + NT * i;
     if (row < n) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
         if (c < nbv) A[row + int64_t(kb + c) * n] = pan[i][c];
     }
   }
-  // apply the row interchanges outside the panel, in order
-  for (int c = 0; c < nbv; ++c) {
-    const int k = kb + c, r = s_piv[c];
-    if (r != k) {
-      for (int j = tid; j < n; j += 512) {
-        if (j >= kb && j < kb + nbv) continue;
-        const double t0 = A[k + int64_t(j) * n];
-        A[k + int64_t(j) * n] = A[r + int64_t(j) * n];
-        A[r + int64_t(j) * n] = t0;
+  // row interchanges outside the panel: every column on its own, in order
+  for (int j = tid; j < n; j += NT) {
+    if (j >= kb && j < kb + nbv) continue;
+    double *col = A + int64_t(j) * n;
+    for (int c = 0; c < nbv; ++c) {
+      const int k = kb + c, r = s_piv[c];
+      if (r != k) {
+        const double t0 = col[k];
+        col[k] = col[r];
+        col[r] = t0;
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // W = pivot rows outside the panel (old values), NB x n, ld NB
   double *W = (double *)bs.d[BUF_SCR] + d.W;
-  for (int e = tid; e < NB * n; e += 512) {
+  for (int e = tid; e < NB * n; e += NT) {
     const int c = e % NB, j = e / NB;
     W[e] = (c < nbv && (j < kb || j >= kb + nbv)) ? A[kb + c + int64_t(j) * n] : 0.0;
   }
   if (tid == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
 }
 
-// Final column interchanges of the blocked Gauss-Jordan: X(:, j) = Y(:, src(j))
-// where src follows the interchanges in reverse order; Y is a copy in scratch.
-__global__ __launch_bounds__(1024) void gj_colperm_src_kernel(
-    const MergeInvDesc *__restrict__ descs, int nd, int32_t *__restrict__ ipiv_all,
-    int32_t *__restrict__ src_all) {
-  const MergeInvDesc &d = descs[blockIdx.x];
-  if (threadIdx.x != 0) return;
-  const int n = d.m;
-  int32_t *src = src_all + d.ipiv;
-  const int32_t *ipiv = ipiv_all + d.ipiv;
-  for (int j = 0; j < n; ++j) src[j] = j;
-  for (int k = n - 1; k >= 0; --k) {
-    const int r = ipiv[k];
-    const int32_t t0 = src[k];
-    src[k] = src[r];
-    src[r] = t0;
-  }
+// G = identity before the first panel
+__global__ __launch_bounds__(256) void gj_ginit_kernel(const MergeInvDesc *__restrict__ descs,
+                                                       int nd, int32_t *__restrict__ g_all) {
+  const MergeInvDesc &d = descs[blockIdx.y];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x)
+    g_all[d.ipiv + i] = i;
 }
 
+// Final column interchanges: Y = X (scratch copy), then X(:, G[i]) = Y(:, i).
 __global__ __launch_bounds__(256) void gj_colperm_copy_kernel(
     const MergeInvDesc *__restrict__ descs, int nd, Bases bs, int to_scratch,
-    const int32_t *__restrict__ src_all) {
+    const int32_t *__restrict__ g_all) {
   const MergeInvDesc &d = descs[blockIdx.y];
   const int n = d.m;
   double *X = (double *)bs.d[BUF_WS] + d.X;
   double *Y = (double *)bs.d[BUF_SCR] + d.W;   // scratch copy (n x n)
-  const int32_t *src = src_all + d.ipiv;
+  const int32_t *G = g_all + d.ipiv;
   const int64_t tot = int64_t(n) * n;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
        e += int64_t(gridDim.x) * blockDim.x) {
@@ -562,7 +632,7 @@ __global__ __launch_bounds__(256) void gj_colperm_copy_kernel(
       Y[e] = X[e];
     } else {
       const int64_t col = e / n, row = e - col * n;
-      X[e] = Y[row + int64_t(src[col]) * n];
+      X[row + int64_t(G[col]) * n] = Y[e];
     }
   }
 }
@@ -570,19 +640,28 @@ __global__ __launch_bounds__(256) void gj_colperm_copy_kernel(
 // ---------------------------------------------------------------------------
 // Solve-stage applies
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double vload(const Bases &bs, const VRef &v, int64_t k,
-                                        int r) {
-  const int64_t idx = v.map >= 0 ? bs.imap[v.map + k] : k;
-  return ((const double *)bs.d[v.buf])[v.off + idx + r * v.stride];
+// Element (k, r) of a vector operand: RHS-major (stride >= 0) at
+// off + idx + r * stride, or RHS-interleaved (stride < 0) at (off + idx) * nrhs + r.
+__device__ __forceinline__ double *vaddr(const Bases &bs, const VRef &v, int64_t k, int r,
+                                         int nrhs) {
+  const int64_t idx = v.off + (v.map >= 0 ? bs.imap[v.map + k] : k);
+  double *b = (double *)bs.d[v.buf];
+  return v.stride >= 0 ? b + idx + r * v.stride : b + idx * nrhs + r;
+}
+
+__device__ __forceinline__ double vload(const Bases &bs, const VRef &v, int64_t k, int r,
+                                        int nrhs) {
+  return *vaddr(bs, v, k, r, nrhs);
 }
 
 template <typename TA, typename TC_, int NR, bool TRANS>
 __global__ __launch_bounds__(256) void apply_kernel(
     const ApplyDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
     int ndesc, int64_t ntiles, Bases bs, int nrhs) {
-  constexpr int KC = 256;
+  constexpr int KC = NR >= 16 ? 64 : 256;
+  constexpr int RC = NR < 8 ? NR : 8;     // RHS per cross-wave reduction round
   __shared__ TC_ Bsh[KC][NR];
-  __shared__ TC_ red[4][64][NR];
+  __shared__ TC_ red[4][64][RC];
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
   const ApplyDesc &d = descs[find_desc_tile0(tile0s, ndesc, tile)];
@@ -606,12 +685,12 @@ __global__ __launch_bounds__(256) void apply_kernel(
       double v = 0.0;
       if (rg < nrhs) {
         if (d.mode == 0) {
-          v = k < d.K1 ? vload(bs, d.B1, k, rg) : vload(bs, d.B2, k - d.K1, rg);
+          v = k < d.K1 ? vload(bs, d.B1, k, rg, nrhs) : vload(bs, d.B2, k - d.K1, rg, nrhs);
         } else if (d.mode == 1) {
-          v = vload(bs, d.B1, k, rg) - vload(bs, d.B2, k, rg);
-          if (d.B3.buf >= 0) v += vload(bs, d.B3, k, rg);
+          v = vload(bs, d.B1, k, rg, nrhs) - vload(bs, d.B2, k, rg, nrhs);
+          if (d.B3.buf >= 0) v += vload(bs, d.B3, k, rg, nrhs);
         } else {
-          v = vload(bs, d.B1, k, rg) + vload(bs, d.B2, k, rg);
+          v = vload(bs, d.B1, k, rg, nrhs) + vload(bs, d.B2, k, rg, nrhs);
         }
       }
       Bsh[kk][r] = TC_(v);
@@ -642,24 +721,27 @@ __global__ __launch_bounds__(256) void apply_kernel(
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) red[wid][lane][r] = acc[r];
-  __syncthreads();
-  if (wid == 0 && row < d.M) {
+  for (int rc = 0; rc < NR; rc += RC) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int rg = r0 + r;
-      if (rg >= nrhs) continue;
-      const double s = double(red[0][lane][r]) + double(red[1][lane][r]) +
-                       double(red[2][lane][r]) + double(red[3][lane][r]);
-      if (d.ksl == 1) {
-        double val = d.alpha * s;
-        if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg);
-        const int64_t ci = d.C.map >= 0 ? bs.imap[d.C.map + row] : row;
-        ((double *)bs.d[d.C.buf])[d.C.off + ci + rg * d.C.stride] = val;
-      } else {
-        ((double *)bs.d[BUF_SCR])[d.part * nrhs + (int64_t(slice) * nrhs + rg) * d.M + row] = s;
+    for (int r = 0; r < RC; ++r) red[wid][lane][r] = acc[rc + r];
+    __syncthreads();
+    if (wid == 0 && row < d.M) {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        const int rg = r0 + rc + r;
+        if (rg >= nrhs) continue;
+        const double s = double(red[0][lane][r]) + double(red[1][lane][r]) +
+                         double(red[2][lane][r]) + double(red[3][lane][r]);
+        if (d.ksl == 1) {
+          double val = d.alpha * s;
+          if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
+          *vaddr(bs, d.C, row, rg, nrhs) = val;
+        } else {
+          ((double *)bs.d[BUF_SCR])[d.part * nrhs + (int64_t(slice) * nrhs + rg) * d.M + row] = s;
+        }
       }
     }
+    __syncthreads();
   }
 }
 
@@ -676,9 +758,8 @@ __global__ __launch_bounds__(256) void apply_finalize_kernel(
     double s = 0.0;
     for (int sl = 0; sl < d.ksl; ++sl) s += part[(int64_t(sl) * nrhs + rg) * d.M + row];
     double val = d.alpha * s;
-    if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg);
-    const int64_t ci = d.C.map >= 0 ? bs.imap[d.C.map + row] : row;
-    ((double *)bs.d[d.C.buf])[d.C.off + ci + rg * d.C.stride] = val;
+    if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
+    *vaddr(bs, d.C, row, rg, nrhs) = val;
   }
 }
 
@@ -690,9 +771,7 @@ __global__ __launch_bounds__(256) void copy_map_kernel(Bases bs, VRef dst, VRef 
        e += int64_t(gridDim.x) * blockDim.x) {
     const int r = int(e / n);
     const int64_t i = e - int64_t(r) * n;
-    const double v = vload(bs, src, i, r);
-    const int64_t di = dst.map >= 0 ? bs.imap[dst.map + i] : i;
-    ((double *)bs.d[dst.buf])[dst.off + di + r * dst.stride] = v;
+    *vaddr(bs, dst, i, r, nrhs) = vload(bs, src, i, r, nrhs);
   }
 }
 
@@ -705,10 +784,9 @@ __global__ __launch_bounds__(256) void vecop_kernel(const VecOpDesc *__restrict_
     const int r = int(e / d.n);
     const int64_t k = e - int64_t(r) * d.n;
     double v = 0.0;
-    if (d.a.buf >= 0) v += d.ca * vload(bs, d.a, k, r);
-    if (d.b.buf >= 0) v += d.cb * vload(bs, d.b, k, r);
-    const int64_t di = d.dst.map >= 0 ? bs.imap[d.dst.map + k] : k;
-    ((double *)bs.d[d.dst.buf])[d.dst.off + di + r * d.dst.stride] = v;
+    if (d.a.buf >= 0) v += d.ca * vload(bs, d.a, k, r, nrhs);
+    if (d.b.buf >= 0) v += d.cb * vload(bs, d.b, k, r, nrhs);
+    *vaddr(bs, d.dst, k, r, nrhs) = v;
   }
 }
 
@@ -820,28 +898,37 @@ hipError_t launch_zdiff(const MergeInvDesc *descs, int nd, int maxm, const Bases
   return hipGetLastError();
 }
 
+int panel_nb(int maxm) { (void)maxm; return 16; }
+
 hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
-                           const Bases &bs, int32_t *ipiv, int32_t *info, hipStream_t st) {
+                           const Bases &bs, int32_t *g, int32_t *info, hipStream_t st) {
   if (nd <= 0) return hipSuccess;
   if (maxm <= 1024)
-    hipLaunchKernelGGL((gj_panel_kernel<kPanelNB, 2>), dim3(nd), dim3(512), 0, st, descs, nd,
-                       kb, bs, ipiv, info);
+    hipLaunchKernelGGL((gj_panel_kernel<16, 2, 512>), dim3(nd), dim3(512), 0, st, descs, nd,
+                       kb, bs, g, info);
   else if (maxm <= 2048)
-    hipLaunchKernelGGL((gj_panel_kernel<kPanelNB, 4>), dim3(nd), dim3(512), 0, st, descs, nd,
-                       kb, bs, ipiv, info);
+    hipLaunchKernelGGL((gj_panel_kernel<16, 4, 512>), dim3(nd), dim3(512), 0, st, descs, nd,
+                       kb, bs, g, info);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
-                             int32_t *ipiv, int32_t *src, hipStream_t st) {
+hipError_t launch_gj_ginit(const MergeInvDesc *descs, int nd, int maxm, int32_t *g,
+                           hipStream_t st) {
   if (nd <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gj_colperm_src_kernel, dim3(nd), dim3(64), 0, st, descs, nd, ipiv, src);
+  hipLaunchKernelGGL(gj_ginit_kernel, dim3(grid_1d(maxm, 64), nd), dim3(256), 0, st, descs, nd, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                             int32_t *g, int32_t *unused, hipStream_t st) {
+  (void)unused;
+  if (nd <= 0) return hipSuccess;
   hipLaunchKernelGGL(gj_colperm_copy_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
-                     dim3(256), 0, st, descs, nd, bs, 1, src);
+                     dim3(256), 0, st, descs, nd, bs, 1, g);
   hipLaunchKernelGGL(gj_colperm_copy_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
-                     dim3(256), 0, st, descs, nd, bs, 0, src);
+                     dim3(256), 0, st, descs, nd, bs, 0, g);
   return hipGetLastError();
 }
 
@@ -849,23 +936,17 @@ template <typename TA, typename TC_, bool TRANS>
 static void launch_apply_t(const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
                            int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st) {
   const int64_t nblk = (ntiles + 7) / 8 * 8;
-  if (nrhs >= 8) {
-    dim3 g(unsigned(nblk), unsigned((nrhs + 7) / 8));
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 8, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
-                       ntiles, bs, nrhs);
-  } else if (nrhs >= 4) {
-    dim3 g(unsigned(nblk), unsigned((nrhs + 3) / 4));
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 4, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
-                       ntiles, bs, nrhs);
-  } else if (nrhs >= 2) {
-    dim3 g(unsigned(nblk), unsigned((nrhs + 1) / 2));
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 2, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
-                       ntiles, bs, nrhs);
-  } else {
-    dim3 g(unsigned(nblk), 1);
-    hipLaunchKernelGGL((apply_kernel<TA, TC_, 1, TRANS>), g, dim3(256), 0, st, descs, tile0s, ndesc,
-                       ntiles, bs, nrhs);
-  }
+#define HPS_APPLY_NR(NRV)                                                                  \
+  hipLaunchKernelGGL((apply_kernel<TA, TC_, NRV, TRANS>),                                 \
+                     dim3(unsigned(nblk), unsigned((nrhs + NRV - 1) / NRV)), dim3(256), 0, st, \
+                     descs, tile0s, ndesc, ntiles, bs, nrhs)
+  if (nrhs > 16) HPS_APPLY_NR(32);
+  else if (nrhs > 8) HPS_APPLY_NR(16);
+  else if (nrhs > 4) HPS_APPLY_NR(8);
+  else if (nrhs > 2) HPS_APPLY_NR(4);
+  else if (nrhs > 1) HPS_APPLY_NR(2);
+  else HPS_APPLY_NR(1);
+#undef HPS_APPLY_NR
 }
 
 hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,

@@ -9,7 +9,8 @@
 
 namespace hps {
 
-constexpr int kPanelNB = 16;   // panel width of the blocked Gauss-Jordan
+constexpr int kPanelNBMax = 32;   // widest panel of the blocked Gauss-Jordan
+int panel_nb(int maxm);           // panel width used for a level of size maxm
 
 hipError_t launch_gemm(const GemmDesc *descs, const int64_t *tile0s, int ndesc,
                        int64_t ntiles, const Bases &bs, hipStream_t st);
@@ -24,6 +25,8 @@ hipError_t launch_zdiff(const MergeInvDesc *descs, int nd, int maxm, const Bases
                         hipStream_t st);
 hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
                            const Bases &bs, int32_t *ipiv, int32_t *info, hipStream_t st);
+hipError_t launch_gj_ginit(const MergeInvDesc *descs, int nd, int maxm, int32_t *g,
+                           hipStream_t st);
 hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
                              int32_t *ipiv, int32_t *src, hipStream_t st);
 hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,

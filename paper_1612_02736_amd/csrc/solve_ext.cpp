@@ -65,14 +65,16 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
   SolveExt &E = *H->ext;
   const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 6;
   const double tol = opts && opts->ir_tol > 0.0 ? opts->ir_tol : 1e-13;
-  const int64_t N = H->pl.n_gauss, vs = H->vec_per_rhs;
+  const int64_t N = H->pl.n_gauss;
   const int64_t ucn = int64_t(H->nleaf) * H->p * H->p;
   // first FP32 pass on the original data
   rc = hps_solve_pass(H, f, g, nrhs, u, 1, nullptr, st);
   if (rc) return rc;
-  double *vug = H->vec.p + H->ug_off;
-  HIPCHK(launch_fill(E.xug.p, 0.0, N * nrhs, st));
-  HIPCHK(launch_accumulate(E.xug.p, N, vug, vs, N, nrhs, 0, st));
+  // the global Gauss vector is RHS-interleaved in BUF_VEC: N * nrhs contiguous
+  double *vug = H->vec.p + H->ug_off * nrhs;
+  const int64_t nug = N * nrhs;
+  HIPCHK(launch_fill(E.xug.p, 0.0, nug, st));
+  HIPCHK(launch_accumulate(E.xug.p, 0, vug, 0, nug, 1, 0, st));
   rc = recompute_exterior(H, u, nrhs, st);
   if (rc) return rc;
   int it = 0;
@@ -82,10 +84,10 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
                            H->aux.p + H->Dh_off, H->aux.p + H->Dh2_off, H->d_lloc.p, H->q, nrhs,
                            st));
     HIPCHK(launch_jump(H->d_jn.p, H->d_fa.p, H->d_fb.p, H->n_jump, E.flux.p,
-                       int64_t(H->nleaf) * H->g4, E.jump.p, N, nrhs, st));
+                       int64_t(H->nleaf) * H->g4, E.jump.p, nrhs, st));
     rc = hps_solve_pass(H, E.zf.p, E.r1.p, nrhs, E.duc.p, 1, E.jump.p, st);
     if (rc) return rc;
-    HIPCHK(launch_accumulate(E.xug.p, N, vug, vs, N, nrhs, 1, st));
+    HIPCHK(launch_accumulate(E.xug.p, 0, vug, 0, nug, 1, 1, st));
     HIPCHK(launch_accumulate(u, ucn, E.duc.p, ucn, ucn, nrhs, 0, st));
     rc = recompute_exterior(H, u, nrhs, st);
     if (rc) return rc;

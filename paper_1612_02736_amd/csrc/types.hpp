@@ -62,8 +62,11 @@ struct MergeInvDesc {
   int64_t ipiv;     // imap-independent int scratch offset (blocked path)
 };
 
-// Vector operand of the solve-stage applies: element (k, r) at
-// base[buf][off + (map >= 0 ? imap[map + k] : k) + r * stride].
+// Vector operand of the solve-stage applies.  With i = off + (map >= 0 ?
+// imap[map + k] : k), element (k, r) is base[buf][i + r * stride] (RHS-major,
+// stride >= 0) or base[buf][i * nrhs + r] (RHS-interleaved, stride < 0).
+constexpr int64_t kInterleaved = -1;
+
 struct VRef {
   int32_t buf;
   int32_t pad;
