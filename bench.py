@@ -149,7 +149,7 @@ def main():
         ev.append((e0, e1, e2))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = debug_profile_read(solver)
+    prof = debug_profile_read(solver, with_work=True)
     debug_profile(solver, False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     factor_ms = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
@@ -189,25 +189,38 @@ def main():
         scale = np.max(np.abs(z["u"]))
         rel_err = float(np.max(np.abs(u[0].cpu().numpy()[z["leaves"]] - z["u"])) / scale)
         rel_err_mixed = float(np.max(np.abs(um[0].cpu().numpy()[z["leaves"]] - z["u"])) / scale)
-    # dominant kernel from the per-launch events of the timed steps
-    agg = {}
-    for kind, var, ms in prof:
+    # dominant kernel from the per-launch events of the timed steps; each
+    # launch carries its algorithmic work (flops, or operator elements applied
+    # to each right-hand side)
+    agg, work = {}, {}
+    for kind, var, ms, w in prof:
         agg.setdefault((kind, var), []).append(ms)
+        work[(kind, var)] = work.get((kind, var), 0.0) + w
     per_step = {k: sum(v) / args.steps for k, v in agg.items()}
+    rates = {}
+    for k, v in agg.items():
+        t = sum(v) * 1e-3
+        if k[0] == "apply":
+            rates[f"{k[0]}[{k[1]}]"] = {"GB/s": 8.0 * work[k] / t / 1e9,
+                                       "TFLOP/s": 2.0 * args.nrhs * work[k] / t / 1e12}
+        elif work[k] > 0:
+            rates[f"{k[0]}[{k[1]}]"] = {"TFLOP/s": work[k] / t / 1e12}
     dom = max(per_step, key=per_step.get)
-    launches = len(agg[dom]) / args.steps
     avg_ms = sum(agg[dom]) / len(agg[dom])
-    if dom == ("gj_leaf", 0):
-        algo = fm["leaf_inv"]
-        roof = {"bound": "alu", "achieved": algo / (avg_ms * 1e-3) / 1e12,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    elif dom[0] == "apply":
-        algo = fm["solve_bytes"] / max(launches, 1)
-        roof = {"bound": "hbm", "achieved": algo / (avg_ms * 1e-3) / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    w_launch = work[dom] / len(agg[dom])
+    if dom[0] == "apply":
+        # operator bytes vs FMA flops of one launch: the larger time decides
+        by = 8.0 * w_launch
+        fl = 2.0 * args.nrhs * w_launch
+        if by / (HBM_PEAK_GBS * 1e9) >= fl / (FP64_PEAK_TFLOPS * 1e12):
+            roof = {"bound": "hbm", "achieved": by / (avg_ms * 1e-3) / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            roof = {"bound": "alu", "achieved": fl / (avg_ms * 1e-3) / 1e12,
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     else:
-        algo = fm["leaf_gemm"] / max(launches, 1)
-        roof = {"bound": "mfma", "achieved": algo / (avg_ms * 1e-3) / 1e12,
+        roof = {"bound": "alu" if dom[0] == "gj_leaf" else "mfma",
+                "achieved": w_launch / (avg_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
@@ -242,6 +255,7 @@ def main():
         "rel_err_vs_oracle": rel_err,
         "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
+        "kernel_rates": rates,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

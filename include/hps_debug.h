@@ -44,12 +44,17 @@ int hps_debug_box_op(const hps_handle *h, int box, int which, double *out, int64
 
 /* Per-launch timing: when enabled, every kernel launch step of builds and
  * solves on this handle is bracketed by HIP events on the caller's stream.
- * hps_debug_profile_read waits for the device, returns (kind, ms) pairs of
- * the steps recorded since the last read (kind = 16 * step type + variant:
- * types 0 GEMM, 1 leaf Gauss-Jordan, 2 interface Gauss-Jordan, 3 interface
- * difference, 4 panel, 5 column permutation, 6 solve apply) and clears them. */
+ * hps_debug_profile_read waits for the device, returns (kind, ms, work)
+ * triples of the steps recorded since the last read (kind = 16 * step type +
+ * variant: types 0 GEMM, 1 leaf Gauss-Jordan, 2 interface Gauss-Jordan,
+ * 3 interface difference, 4 panel, 5 column permutation, 6 solve apply) and
+ * clears them.  work is the launch's algorithmic flop count (GEMM,
+ * Gauss-Jordan, panel) or the number of operator elements it applies to each
+ * right-hand side (apply); `work` may be NULL.  Host arrays of max_n entries;
+ * *count receives the number recorded. */
 int hps_debug_profile(hps_handle *h, int enable);
-int hps_debug_profile_read(hps_handle *h, int *kinds, double *ms, int max_n, int *count);
+int hps_debug_profile_read(hps_handle *h, int *kinds, double *ms, double *work, int max_n,
+                           int *count);
 
 #ifdef __cplusplus
 }

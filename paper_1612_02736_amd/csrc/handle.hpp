@@ -66,6 +66,9 @@ struct Step {
   int64_t fin0 = 0, nfin = 0;  // APPLY: finalize list range
   int64_t fin_maxm = 0;
   bool trans = false;         // APPLY: transposed operator
+  // Algorithmic work of the launch: flops (GEMM, Gauss-Jordan, panel) or
+  // operator elements read per right-hand side (APPLY).
+  double work = 0.0;
 };
 
 
@@ -104,6 +107,8 @@ struct hps_handle {
   // flux-jump residual maps (uniform trees): interior node id, flux index of
   // the west/south leaf and of the east/north leaf
   hps::DevArray<int32_t> d_jn, d_fa, d_fb;
+  std::vector<int32_t> h_jn, h_fa, h_fb;   // host copies, uploaded by hps_build
+  std::vector<double> h_lloc;
   int64_t n_jump = 0;
   bool conforming = true;     // no refined interfaces
   hps::DevArray<double> d_lloc;   // q x p row-major Chebyshev -> Gauss
@@ -123,6 +128,7 @@ struct hps_handle {
   // optional per-step timing (test hook): events around every launch step
   bool prof_on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
+  std::vector<double> prof_work;
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
   std::unique_ptr<hps::SolveExt, hps::SolveExtDeleter> ext;

@@ -1068,12 +1068,11 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         }
     }
     H->n_jump = (int64_t)jn.size();
-    if (H->d_jn.upload(jn) != hipSuccess || H->d_fa.upload(fa) != hipSuccess ||
-        H->d_fb.upload(fb) != hipSuccess)
-      return fail(HPS_EHIP, "upload of residual maps");
+    H->h_jn = std::move(jn);
+    H->h_fa = std::move(fa);
+    H->h_fb = std::move(fb);
     std::vector<double> xc = cheb_points(p), xg = legendre_roots(q);
-    std::vector<double> Lloc = interp_matrix(xc, xg);
-    if (H->d_lloc.upload(Lloc) != hipSuccess) return fail(HPS_EHIP, "upload of L_loc");
+    H->h_lloc = interp_matrix(xc, xg);
   }
   H->part_per_rhs = part_off;
   H->off_T = Lo.T; H->off_X = Lo.X; H->off_S = Lo.S; H->off_LD = Lo.LD; H->off_H = Lo.H;
@@ -1089,6 +1088,32 @@ Bases make_bases(hps_handle *H) {
   b.d[BUF_AUX] = H->aux.p;
   b.imap = H->imap.p;
   return b;
+}
+
+// Algorithmic work of each launch step, from the host descriptor lists.
+static void annotate_work(std::vector<Step> &prog, const GemmList &gl,
+                          const std::vector<MergeInvDesc> &mv,
+                          const std::vector<ApplyDesc> &ap, int mi) {
+  for (Step &s : prog) {
+    double w = 0.0;
+    for (int64_t i = s.d0; i < s.d0 + s.nd; ++i) {
+      switch (s.kind) {
+        case S_GEMM: w += 2.0 * gl.d[i].M * double(gl.d[i].N) * gl.d[i].K; break;
+        case S_GJ_LEAF: w += 2.0 * double(mi) * mi * mi; break;
+        case S_GJ_MERGE: w += 2.0 * double(mv[i].m) * mv[i].m * mv[i].m; break;
+        case S_PANEL: {
+          const double nb = std::min(panel_nb(s.maxm), mv[i].m - s.kb);
+          if (nb > 0) w += 2.0 * mv[i].m * nb * nb;
+          break;
+        }
+        case S_APPLY:
+          w += double(ap[i].M) * (ap[i].K1 + (ap[i].mode == 0 ? ap[i].K2 : 0));
+          break;
+        default: break;
+      }
+    }
+    s.work = w;
+  }
 }
 
 static hipEvent_t prof_event(hps_handle *H) {
@@ -1152,6 +1177,7 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
       int kind = int(s.kind) * 16 + (s.kind == S_GJ_MERGE ? s.cls : 0);
       if (s.kind == S_APPLY) kind += prec;
       H->prof_ev.push_back({kind, {e0, e1}});
+      H->prof_work.push_back(s.work);
     }
   }
   return HPS_OK;
@@ -1215,6 +1241,9 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   rc = plan_handle(H.get(), Lo, aux_init, blocks, imap, gl, leafd, minv, appl, appl_t0, finlist,
                    vops);
   if (rc) return rc;
+  for (auto *prog : {&H->build_prog, &H->up_prog, &H->down_prog, &H->adj_down_prog,
+                     &H->adj_up_prog, &H->up_jump_prog, &H->ext_prog})
+    annotate_work(*prog, gl, minv, appl, H->mi);
   H->solve_elems = (size_t)Lo.solve_ws;
   H->scr_build = Lo.scr + 64;
   if (H->ws.alloc(Lo.ws) != hipSuccess || H->scr.alloc(Lo.scr + 64) != hipSuccess)
@@ -1236,6 +1265,10 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   HIPCHK(H->d_apply_t0.upload(appl_t0));
   HIPCHK(H->d_finlist.upload(finlist));
   HIPCHK(H->d_vecop.upload(vops));
+  HIPCHK(H->d_jn.upload(H->h_jn));
+  HIPCHK(H->d_fa.upload(H->h_fa));
+  HIPCHK(H->d_fb.upload(H->h_fb));
+  HIPCHK(H->d_lloc.upload(H->h_lloc));
   // keep the coefficients (residuals of mixed-precision solves use them)
   const size_t ncoef = size_t(H->nleaf) * 6 * p * p;
   HIPCHK(H->coef.alloc(ncoef));
@@ -1476,12 +1509,13 @@ extern "C" int hps_debug_profile(hps_handle *h, int enable) {
   if (!h) return fail(HPS_EINVAL, "NULL handle");
   h->prof_on = enable != 0;
   h->prof_ev.clear();
+  h->prof_work.clear();
   h->prof_used = 0;
   return HPS_OK;
 }
 
-extern "C" int hps_debug_profile_read(hps_handle *h, int *kinds, double *ms, int max_n,
-                                      int *count) {
+extern "C" int hps_debug_profile_read(hps_handle *h, int *kinds, double *ms, double *work,
+                                      int max_n, int *count) {
   if (!h || !count) return fail(HPS_EINVAL, "NULL argument");
   HIPCHK(hipDeviceSynchronize());
   const int n = std::min<int>(max_n, (int)h->prof_ev.size());
@@ -1490,9 +1524,11 @@ extern "C" int hps_debug_profile_read(hps_handle *h, int *kinds, double *ms, int
     HIPCHK(hipEventElapsedTime(&t, h->prof_ev[i].second.first, h->prof_ev[i].second.second));
     kinds[i] = h->prof_ev[i].first;
     ms[i] = t;
+    if (work) work[i] = h->prof_work[i];
   }
   *count = (int)h->prof_ev.size();
   h->prof_ev.clear();
+  h->prof_work.clear();
   h->prof_used = 0;
   return HPS_OK;
 }

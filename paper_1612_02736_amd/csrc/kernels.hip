@@ -189,38 +189,43 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
 // Register-resident Gauss-Jordan inversion
 // ---------------------------------------------------------------------------
 // Threads per workgroup of the register-resident kernels: TR*TC rounded up to
-// whole wavefronts, so every wavefront of the pivot search has all lanes
-// active; the extra threads own no rows or columns.
+// whole wavefronts, so every wavefront has all lanes active.  The extra
+// threads repeat the first threads' rows and columns: they compute the same
+// values and store the same values to the same places.
 template <int TR, int TC>
 constexpr int gj_threads() { return (TR * TC + 63) / 64 * 64; }
 
 template <int TR, int TC, int RA, int CB>
 __device__ __forceinline__ void gj_owner(int tid, int &tr, int &tc) {
-  if (tid < TR * TC) { tr = tid % TR; tc = tid / TR; }
-  else { tr = TR * RA; tc = TC * CB; }
+  const int t = tid < TR * TC ? tid : tid - TR * TC;
+  tr = t % TR;
+  tc = t / TR;
 }
 
 template <int TR, int TC, int RA, int CB>
 struct GJShared {
   double colbuf[2][TR * RA];
   double rowbuf[TC * CB];
+  double sig[TR * RA];              // 1 / pivot of step k
   unsigned long long cand[2][2];
   int pivrow[TR * RA];
   int stepof[TR * RA];
   int info;
 };
 
-// Pivot candidate of column c among the unused rows owned by the TR threads
-// of column owner tc = c mod TC (a contiguous run of TR threads that spans
-// one or two wavefronts).  Each of those wavefronts reduces its lanes and
-// lane 0 stores the result in slot 0 (first wavefront of the run) or 1.
+// Pivot candidate of column ctc + TC*slot among the unused rows, held by the TR
+// threads with tc == ctc (a contiguous run of TR threads that spans one or two
+// wavefronts).  Each of those wavefronts reduces its lanes and lane 0 stores
+// the result in slot 0 (first wavefront of the run) or 1.  Padding rows are
+// marked used in umask from the start.  The keys of one thread's rows differ
+// from pivot_key(x, tr + TR*i) by the common offset tr in the row field, which
+// is subtracted after the thread's own maximum is taken.
 template <int TR, int TC, int RA, int CB>
 __device__ __forceinline__ void gj_candidate(const double (&a)[RA][CB], const unsigned umask,
-                                             const int n, const int c, const int tr,
+                                             const int ctc, const int slot, const int tr,
                                              const int tc, GJShared<TR, TC, RA, CB> &sh,
                                              const int par) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int cb = c / TC, ctc = c - cb * TC;
   const int lo = ctc * TR, hi = lo + TR - 1;          // owner thread range
   const int wlo = lo >> 6, whi = hi >> 6;
   if (wid < wlo || wid > whi) return;                 // uniform per wavefront
@@ -228,15 +233,14 @@ __device__ __forceinline__ void gj_candidate(const double (&a)[RA][CB], const un
   if (tc == ctc) {
 #pragma unroll
     for (int i = 0; i < RA; ++i) {
-      const int row = tr + TR * i;
-      if (row < n && !((umask >> i) & 1u)) {
-        double x = 0.0;
+      double x = 0.0;
 #pragma unroll
-        for (int b = 0; b < CB; ++b) if (b == cb) x = a[i][b];
-        const unsigned long long k2 = pivot_key(x, row);
-        key = k2 > key ? k2 : key;
-      }
+      for (int b = 0; b < CB; ++b) if (b == slot) x = a[i][b];
+      const unsigned long long k2 =
+          ((umask >> i) & 1u) ? 0ull : pivot_key(x, TR * i);   // bits >= 16 hold tc
+      key = k2 > key ? k2 : key;
     }
+    if (key) key -= (unsigned long long)tr;
   }
   key = wave_max_u64(key);
   if (lane == 0) {
@@ -245,106 +249,111 @@ __device__ __forceinline__ void gj_candidate(const double (&a)[RA][CB], const un
   }
 }
 
-// Thread (tr, tc) owns rows tr + TR*i and columns tc + TC*b.  On exit the
-// registers hold the swept matrix M with M[r_k][k'] = inv[k][r_k'] where r_k
-// is the pivot row of step k.
+// In-place Gauss-Jordan sweeps with implicit partial pivoting.  Thread
+// (tr, tc) owns rows tr + TR*i and columns tc + TC*b.
+//
+// Step k = TC*kb + kk eliminates column k, which sits in register slot kb of
+// the threads with tc == kk.  The outer loop over kb is unrolled so that the
+// slot is a compile-time constant.  Rows and columns >= n of the padded block
+// start at 0 and stay 0 (each update multiplies by a zero row or column
+// entry), so no bounds tests are needed.
+//
+// Pivot rows are kept unscaled: if sig_r = 1 / pivot of the step that chose
+// row r, the swept matrix M of the textbook algorithm has
+//   M[r][j] = sig_r * (a[r][j] + [j == k_r])
+// where k_r is that step.  This is consistent because a sweep is homogeneous
+// in each row (a row and its entry in the pivot column scale together), a
+// pivot row needs no update in its own step (its pivot-column entry is
+// published as 0), and the entry (r, k_r) never feeds another entry, so its
+// unit value of the textbook algorithm can be added at the end.  On exit
+// M[r_k][k'] = inv[k][r_k'] where r_k is the pivot row of step k.
 template <int TR, int TC, int RA, int CB>
 __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
                                         const int tr, const int tc,
                                         GJShared<TR, TC, RA, CB> &sh) {
   const int tid = threadIdx.x;
-  unsigned umask = 0u;                                // used rows among my RA rows
+  // bits 0..RA-1: used rows among my RA rows; bits 16..: tc (one register for
+  // both keeps the step loop within 128 VGPRs)
+  unsigned umask = unsigned(tc) << 16;
+#pragma unroll
+  for (int i = 0; i < RA; ++i)
+    if (tr + TR * i >= n) umask |= 1u << i;
   if (tid == 0) sh.info = 0;
   if (tc == 0) {
 #pragma unroll
-    for (int i = 0; i < RA; ++i) {
-      const int row = tr + TR * i;
-      if (row < n) sh.colbuf[0][row] = a[i][0];
-    }
+    for (int i = 0; i < RA; ++i) sh.colbuf[0][tr + TR * i] = a[i][0];
   }
-  gj_candidate<TR, TC, RA, CB>(a, umask, n, 0, tr, tc, sh, 0);
+  gj_candidate<TR, TC, RA, CB>(a, umask, 0, 0, tr, tc, sh, 0);
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const int par = k & 1;
-    const double *cb = sh.colbuf[par];
-    const unsigned long long k0 = sh.cand[par][0], k1c = sh.cand[par][1];
-    const int r = __builtin_amdgcn_readfirstlane(key_row(k0 > k1c ? k0 : k1c));
-    const double piv = cb[r];
-    const int ir = r / TR;
-    const bool rown = (tr == r - ir * TR);
-    if (rown) {
+#pragma unroll
+  for (int kb = 0; kb < CB; ++kb) {
+    const int kend = min(TC, n - kb * TC);
+    for (int kk = 0; kk < kend; ++kk) {
+      const int k = kb * TC + kk;
+      const int par = k & 1;
+      double *cb = sh.colbuf[par];
+      const unsigned long long k0 = sh.cand[par][0], k1c = sh.cand[par][1];
+      const int r = __builtin_amdgcn_readfirstlane(key_row(k0 > k1c ? k0 : k1c));
+      const int ir = __builtin_amdgcn_readfirstlane(r / TR);
+      const bool rown = (tr == r - ir * TR);
+      // publish the pivot row; its own entry of the pivot column becomes 0
 #pragma unroll
       for (int i = 0; i < RA; ++i)
-        if (i == ir) {
+        if (i == ir && rown) {
 #pragma unroll
-          for (int b = 0; b < CB; ++b) {
-            const int col = tc + TC * b;
-            if (col < n) sh.rowbuf[col] = a[i][b];
-          }
+          for (int b = 0; b < CB; ++b) sh.rowbuf[int(umask >> 16) + TC * b] = a[i][b];
         }
-      umask |= 1u << ir;
-    }
-    const bool ok = (piv != 0.0) && isfinite(piv);
-    if (tid == 0) {
-      sh.pivrow[k] = r;
-      sh.stepof[r] = k;
-      if (!ok && sh.info == 0) sh.info = isfinite(piv) ? (k + 1) : -(k + 1);
-    }
-    __syncthreads();
-    const double ip = ok ? 1.0 / piv : 0.0;
-    double s[CB];
+      if (rown) umask |= 1u << ir;
+      if (tid == 0) {
+        sh.pivrow[k] = r;
+        sh.stepof[r] = k;
+        cb[r] = 0.0;
+      }
+      __syncthreads();
+      const double piv = sh.rowbuf[k];
+      const bool ok = (piv != 0.0) && isfinite(piv);
+      const double ip = ok ? 1.0 / piv : 0.0;
+      if (tid == 0) {
+        sh.sig[k] = ip;
+        if (!ok && sh.info == 0) sh.info = isfinite(piv) ? (k + 1) : -(k + 1);
+      }
+      double s[CB];
 #pragma unroll
-    for (int b = 0; b < CB; ++b) {
-      const int col = tc + TC * b;
-      s[b] = (col < n) ? sh.rowbuf[col] * ip : 0.0;
-    }
+      for (int b = 0; b < CB; ++b) s[b] = sh.rowbuf[int(umask >> 16) + TC * b] * ip;
 #pragma unroll
-    for (int i = 0; i < RA; ++i) {
-      const int row = tr + TR * i;
-      const double f = (row < n) ? cb[row] : 0.0;
+      for (int i = 0; i < RA; ++i) {
+        const double f = cb[tr + TR * i];
 #pragma unroll
-      for (int b = 0; b < CB; ++b) a[i][b] = fma(-f, s[b], a[i][b]);
-    }
-    const int kb = k / TC;
-    const bool kown = (tc == k - kb * TC);
-    if (kown) {
+        for (int b = 0; b < CB; ++b) a[i][b] = fma(-f, s[b], a[i][b]);
+      }
+      if (int(umask >> 16) == kk) {
 #pragma unroll
-      for (int b = 0; b < CB; ++b)
-        if (b == kb) {
+        for (int i = 0; i < RA; ++i) a[i][kb] = -cb[tr + TR * i] * ip;
+      }
+      if (kk + 1 < kend) {
+        if (int(umask >> 16) == kk + 1) {
+#pragma unroll
+          for (int i = 0; i < RA; ++i) sh.colbuf[par ^ 1][tr + TR * i] = a[i][kb];
+        }
+        gj_candidate<TR, TC, RA, CB>(a, umask, kk + 1, kb, tr, int(umask >> 16), sh, par ^ 1);
+      } else if (kb + 1 < CB && k + 1 < n) {
+        if (int(umask >> 16) == 0) {
 #pragma unroll
           for (int i = 0; i < RA; ++i) {
-            const int row = tr + TR * i;
-            a[i][b] = (row < n) ? -cb[row] * ip : 0.0;
+            double x = 0.0;
+#pragma unroll
+            for (int b = 0; b < CB; ++b) if (b == kb + 1) x = a[i][b];
+            sh.colbuf[par ^ 1][tr + TR * i] = x;
           }
         }
-    }
-    if (rown) {
-#pragma unroll
-      for (int i = 0; i < RA; ++i)
-        if (i == ir) {
-#pragma unroll
-          for (int b = 0; b < CB; ++b) a[i][b] = (kown && b == kb) ? ip : s[b];
-        }
-    }
-    if (k + 1 < n) {
-      const int k1 = k + 1, kb1 = k1 / TC;
-      if (tc == k1 - kb1 * TC) {
-#pragma unroll
-        for (int b = 0; b < CB; ++b)
-          if (b == kb1) {
-#pragma unroll
-            for (int i = 0; i < RA; ++i) {
-              const int row = tr + TR * i;
-              if (row < n) sh.colbuf[k1 & 1][row] = a[i][b];
-            }
-          }
+        gj_candidate<TR, TC, RA, CB>(a, umask, 0, kb + 1, tr, int(umask >> 16), sh, par ^ 1);
       }
-      gj_candidate<TR, TC, RA, CB>(a, umask, n, k1, tr, tc, sh, k1 & 1);
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
+// X[k][r_k'] = M[r_k][k'] with M from the unscaled sweep (see gj_core).
 template <int TR, int TC, int RA, int CB>
 __device__ __forceinline__ void gj_store(const double (&a)[RA][CB], const int n,
                                          const int tr, const int tc,
@@ -354,11 +363,14 @@ __device__ __forceinline__ void gj_store(const double (&a)[RA][CB], const int n,
   for (int i = 0; i < RA; ++i) {
     const int row = tr + TR * i;
     if (row >= n) continue;
-    const int64_t orow = sh.stepof[row];
+    const int kr = sh.stepof[row];
+    const double sg = sh.sig[kr];
+    const int64_t orow = kr;
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       const int col = tc + TC * b;
-      if (col < n) X[orow + int64_t(sh.pivrow[col]) * ldx] = a[i][b];
+      if (col < n)
+        X[orow + int64_t(sh.pivrow[col]) * ldx] = sg * (a[i][b] + (col == kr ? 1.0 : 0.0));
     }
   }
 }

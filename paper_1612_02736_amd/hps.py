@@ -321,19 +321,26 @@ def debug_profile(solver, enable=True):
     if not hasattr(L, "_prof"):
         L.hps_debug_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.hps_debug_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                             ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+                                             ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int)]
         L._prof = True
     _check(L.hps_debug_profile(solver._h, int(enable)))
 
 
-def debug_profile_read(solver, max_n=100000):
-    """[(kind, variant, ms)] of every launch step since the last read."""
+def debug_profile_read(solver, max_n=100000, with_work=False):
+    """[(kind, variant, ms)] of every launch step since the last read, or
+    [(kind, variant, ms, work)] with the launch's algorithmic work (flops, or
+    operator elements per right-hand side for applies)."""
     L = _debug_lib()
     kinds = np.zeros(max_n, dtype=np.int32)
     ms = np.zeros(max_n)
+    work = np.zeros(max_n)
     n = ctypes.c_int()
-    _check(L.hps_debug_profile_read(solver._h, _np_ptr(kinds), _np_ptr(ms), max_n,
+    _check(L.hps_debug_profile_read(solver._h, _np_ptr(kinds), _np_ptr(ms), _np_ptr(work), max_n,
                                     ctypes.byref(n)))
     k = min(n.value, max_n)
-    return [(PROFILE_KINDS.get(int(kinds[i]) // 16, "?"), int(kinds[i]) % 16, float(ms[i]))
-            for i in range(k)]
+    out = []
+    for i in range(k):
+        t = (PROFILE_KINDS.get(int(kinds[i]) // 16, "?"), int(kinds[i]) % 16, float(ms[i]))
+        out.append(t + (float(work[i]),) if with_work else t)
+    return out
