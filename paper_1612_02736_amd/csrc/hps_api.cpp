@@ -314,26 +314,26 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
     Step s{S_PANEL};
     s.d0 = d0; s.nd = (int64_t)big.size(); s.kb = kb; s.maxm = bigmax;
     prog.push_back(s);
+    // columns outside the panel: B <- B + P W (the panel kernel has zeroed
+    // the pivot rows of B and copied their old values to W)
     GemmList up;
     for (const MergeInvDesc &d : big) {
       const int m = d.m;
       if (kb >= m) continue;
       const int nbv = std::min(NBp, m - kb), ke = kb + nbv;
-      const int rows[3][2] = {{0, kb}, {kb, ke}, {ke, m}};
       const int cols[2][2] = {{0, kb}, {ke, m}};
-      for (int ri = 0; ri < 3; ++ri)
-        for (int ci = 0; ci < 2; ++ci) {
-          const int r0 = rows[ri][0], r1 = rows[ri][1], c0 = cols[ci][0], c1 = cols[ci][1];
-          if (r1 <= r0 || c1 <= c0) continue;
-          GemmDesc g{};
-          g.M = r1 - r0; g.N = c1 - c0; g.K = nbv;
-          g.A = ref(BUF_WS, d.X + r0 + int64_t(kb) * m, m);
-          g.B = ref(BUF_SCR, d.W + int64_t(c0) * NBp, NBp);
-          g.C = ref(BUF_WS, d.X + r0 + int64_t(c0) * m, m);
-          g.D = (ri == 1) ? noref() : ref(BUF_WS, d.X + r0 + int64_t(c0) * m, m);
-          g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = (ri == 1) ? 0.0 : 1.0;
-          up.add(g);
-        }
+      for (int ci = 0; ci < 2; ++ci) {
+        const int c0 = cols[ci][0], c1 = cols[ci][1];
+        if (c1 <= c0) continue;
+        GemmDesc g{};
+        g.M = m; g.N = c1 - c0; g.K = nbv;
+        g.A = ref(BUF_WS, d.X + int64_t(kb) * m, m);
+        g.B = ref(BUF_SCR, d.W + int64_t(c0) * NBp, NBp);
+        g.C = ref(BUF_WS, d.X + int64_t(c0) * m, m);
+        g.D = ref(BUF_WS, d.X + int64_t(c0) * m, m);
+        g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 1.0;
+        up.add(g);
+      }
     }
     gemm_step(gl, up, prog);
   }
@@ -466,8 +466,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
     if (gj_merge_class(m) < 0) {
       Lo.W_scr[b] = scr_take(std::max<int64_t>(int64_t(kPanelNBMax) * m, int64_t(m) * m));
-      Lo.ipiv[b] = Lo.ipiv_n;
-      Lo.ipiv_n += m;
+      Lo.ipiv[b] = Lo.ipiv_n;          // pivrow[m], stepof[m]
+      Lo.ipiv_n += 2 * int64_t(m);
     }
     if (B.coarsened && B.parent >= 0) {
       Lo.Tn_scr[b] = scr_take(int64_t(en) * en);
@@ -1428,7 +1428,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   HIPCHK(launch_fill(H.ws.p + nn * batch, 0.0, nn, st));
   const int64_t wsz = std::max<int64_t>(int64_t(kPanelNBMax) * n, nn);
   HIPCHK(H.scr.alloc(size_t(wsz) * batch + 64));
-  HIPCHK(H.ipiv.alloc(size_t(n) * batch));
+  HIPCHK(H.ipiv.alloc(size_t(2 * n) * batch));
   HIPCHK(H.psrc.alloc(size_t(n) * batch));
   HIPCHK(H.info.alloc(batch));
   HIPCHK(hipMemsetAsync(H.info.p, 0, sizeof(int32_t) * batch, st));
@@ -1436,7 +1436,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   for (int b = 0; b < batch; ++b) {
     MergeInvDesc d{};
     d.Ta = nn * b; d.Tb = nn * batch; d.lda = n; d.ldb = n; d.m = n; d.info = b;
-    d.X = nn * (batch + 1 + b); d.W = wsz * b; d.ipiv = int64_t(n) * b;
+    d.X = nn * (batch + 1 + b); d.W = wsz * b; d.ipiv = int64_t(2 * n) * b;
     lev.push_back(d);
   }
   GemmList gl;

@@ -44,41 +44,36 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Pivot search keys: |x| (non-negative, so its bit pattern orders like the
-// value) with the low 12 mantissa bits replaced by 4095 - row.  The largest
-// key is the largest |x| (to 2^-40 relative) and, among those, the lowest row;
-// rows that are not candidates carry key 0.  NaN keys exceed every finite key,
-// so a NaN pivot is found and reported.
-__device__ __forceinline__ unsigned long long pivot_key(double x, int row) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(x));
-  return (b & ~0xFFFull) | (unsigned long long)(4095 - row);
+// Pivot search keys (32 bits): the high word of |x| (non-negative, so its bit
+// pattern orders like the value) with its low 12 bits replaced by 4095 - row.
+// The largest key is an |x| within a factor 1 - 2^-8 of the largest (the
+// 11 exponent bits and 8 leading mantissa bits are compared) and, among
+// those, the lowest row: threshold partial pivoting with threshold 1 - 2^-8.
+// Rows that are not candidates carry key 0.  NaN and infinite entries exceed
+// every finite key, so a non-finite pivot is found and reported.
+__device__ __forceinline__ unsigned pivot_key(double x, int row) {
+  const unsigned hi = unsigned((unsigned long long)__double_as_longlong(x) >> 32) & 0x7FFFFFFFu;
+  return (hi & ~0xFFFu) | unsigned(4095 - row);
 }
-__device__ __forceinline__ int key_row(unsigned long long k) { return 4095 - int(k & 0xFFFull); }
+__device__ __forceinline__ int key_row(unsigned k) { return 4095 - int(k & 0xFFFu); }
 
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, false);
-  return (unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32);
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_max_u32(unsigned v) {
+  const unsigned o = unsigned(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWS, 0xF, false));
+  return o > v ? o : v;
 }
 
-// Maximum of a 64-bit key over the 64 lanes, returned wave-uniform: DPP
-// butterflies inside each 16-lane row, then the four row results by readlane.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  unsigned long long o;
-  o = dpp_u64<0xB1>(v);  v = o > v ? o : v;     // quad_perm [1,0,3,2]
-  o = dpp_u64<0x4E>(v);  v = o > v ? o : v;     // quad_perm [2,3,0,1]
-  o = dpp_u64<0x141>(v); v = o > v ? o : v;     // row_half_mirror
-  o = dpp_u64<0x140>(v); v = o > v ? o : v;     // row_mirror
-  unsigned long long m = 0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const unsigned lo = __builtin_amdgcn_readlane(int(unsigned(v)), 16 * r);
-    const unsigned hi = __builtin_amdgcn_readlane(int(unsigned(v >> 32)), 16 * r);
-    const unsigned long long x = (unsigned long long)lo | ((unsigned long long)hi << 32);
-    m = x > m ? x : m;
-  }
-  return m;
+// Maximum of a 32-bit key over the 64 lanes, returned wave-uniform: DPP
+// butterflies inside each 16-lane row, then row_bcast:15 and row_bcast:31 fold
+// the rows into lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = dpp_max_u32<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+  v = dpp_max_u32<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+  v = dpp_max_u32<0x141, 0xF>(v);    // row_half_mirror
+  v = dpp_max_u32<0x140, 0xF>(v);    // row_mirror
+  v = dpp_max_u32<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+  v = dpp_max_u32<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+  return unsigned(__builtin_amdgcn_readlane(int(v), 63));
 }
 
 // ---------------------------------------------------------------------------
@@ -207,7 +202,7 @@ struct GJShared {
   double colbuf[2][TR * RA];
   double rowbuf[TC * CB];
   double sig[TR * RA];              // 1 / pivot of step k
-  unsigned long long cand[2][2];
+  unsigned cand[2][2];
   int pivrow[TR * RA];
   int stepof[TR * RA];
   int info;
@@ -229,20 +224,19 @@ __device__ __forceinline__ void gj_candidate(const double (&a)[RA][CB], const un
   const int lo = ctc * TR, hi = lo + TR - 1;          // owner thread range
   const int wlo = lo >> 6, whi = hi >> 6;
   if (wid < wlo || wid > whi) return;                 // uniform per wavefront
-  unsigned long long key = 0;
+  unsigned key = 0;
   if (tc == ctc) {
 #pragma unroll
     for (int i = 0; i < RA; ++i) {
       double x = 0.0;
 #pragma unroll
       for (int b = 0; b < CB; ++b) if (b == slot) x = a[i][b];
-      const unsigned long long k2 =
-          ((umask >> i) & 1u) ? 0ull : pivot_key(x, TR * i);   // bits >= 16 hold tc
+      const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(x, TR * i);   // bits >= 16 hold tc
       key = k2 > key ? k2 : key;
     }
-    if (key) key -= (unsigned long long)tr;
+    if (key) key -= unsigned(tr);
   }
-  key = wave_max_u64(key);
+  key = wave_max_u32(key);
   if (lane == 0) {
     sh.cand[par][wid == wlo ? 0 : 1] = key;
     if (wlo == whi) sh.cand[par][1] = 0;
@@ -292,7 +286,7 @@ __device__ __forceinline__ void gj_core(double (&a)[RA][CB], const int n,
       const int k = kb * TC + kk;
       const int par = k & 1;
       double *cb = sh.colbuf[par];
-      const unsigned long long k0 = sh.cand[par][0], k1c = sh.cand[par][1];
+      const unsigned k0 = sh.cand[par][0], k1c = sh.cand[par][1];
       const int r = __builtin_amdgcn_readfirstlane(key_row(k0 > k1c ? k0 : k1c));
       const int ir = __builtin_amdgcn_readfirstlane(r / TR);
       const bool rown = (tr == r - ir * TR);
@@ -480,114 +474,107 @@ __global__ __launch_bounds__(256) void zdiff_kernel(const MergeInvDesc *__restri
   }
 }
 
-// One workgroup per matrix: unblocked Gauss-Jordan on the NB columns
-// [kb, kb+NB) held in registers (row t + NT i owned by thread t), pivot rows
-// chosen among rows >= k, rows interchanged across the whole matrix, then the
-// old pivot rows outside the panel copied to W (NB x m, ld NB) for the
-// rank-NB update.  The inverse of the accumulated row permutation is kept in
-// G (G[k] <-> G[r] per interchange); the final inverse is X(:, G[i]) = Y(:, i).
+// Blocked Gauss-Jordan with implicit partial pivoting (no row interchanges).
+// For the NB columns [kb, kb+NB) one workgroup per matrix sweeps the panel
+// held in registers (row t + NT i owned by thread t): the pivot row of column
+// k is the unused row of largest magnitude, and the sweep is the textbook one
+// restricted to the panel columns.  If R is the set of the panel's pivot rows
+// and L the product of its elementary sweep matrices, L differs from I only
+// in the columns R and the swept panel column c holds L(:, r_c).  The other
+// columns therefore become L * B = (B with rows R set to 0) + P W where
+// W(c, :) = B(r_c, :): gj_wgather_kernel copies W (NB x m, ld NB) and zeroes
+// the rows R outside the panel; the product P W is a GEMM.  After the last panel
+// the swept matrix M has M[r_k][k'] = inv[k][r_k'], which gj_perm_kernel
+// turns into the inverse.  pivrow[k] = r_k and stepof[r] = the step that
+// used row r (-1 before) live in int scratch.
+//
+// One barrier per column: every wavefront's best candidate row travels to LDS
+// with its key, so after the barrier all threads read the pivot row from the
+// winning wavefront's slot.
 template <int NB, int RPT, int NT>
 __global__ __launch_bounds__(NT) void gj_panel_kernel(
     const MergeInvDesc *__restrict__ descs, int nd, int kb, Bases bs,
     int32_t *__restrict__ g_all, int32_t *__restrict__ info) {
   constexpr int NW = NT / 64;
-  __shared__ unsigned long long wkey[NW];
-  __shared__ double prow[NB];
-  __shared__ double srow[NB];
-  __shared__ int s_piv[NB];
+  __shared__ unsigned wkey[2][NW];
+  __shared__ double crow[2][NW][NB];
   const MergeInvDesc &d = descs[blockIdx.x];
   const int n = d.m;
   if (kb >= n) return;
   const int nbv = min(NB, n - kb);
   double *A = (double *)bs.d[BUF_WS] + d.X;
-  int32_t *G = g_all + d.ipiv;
+  int32_t *pivrow = g_all + d.ipiv;
+  int32_t *stepof = pivrow + n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double pan[RPT][NB];
+  unsigned umask = 0u;          // rows already used as pivots (or padding)
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = tid + NT * i;
+    const bool in = row < n;
+    if (!in || stepof[row] >= 0) umask |= 1u << i;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      pan[i][c] = (row < n && c < nbv) ? A[row + int64_t(kb + c) * n] : 0.0;
+      pan[i][c] = (in && c < nbv) ? A[row + int64_t(kb + c) * n] : 0.0;
   }
   int first_bad = 0;
-  for (int c = 0; c < nbv; ++c) {
-    const int k = kb + c;
-    unsigned long long key = 0;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int row = tid + NT * i;
-      if (row >= k && row < n) {
-        double x = 0.0;
+  for (int c = 0; c < NB; ++c) {
+    if (c < nbv) {
+      const int par = c & 1;
+      unsigned key = 0;
+      int bi = 0;
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) if (cc == c) x = pan[i][cc];
-        const unsigned long long k2 = pivot_key(x, row);
-        key = k2 > key ? k2 : key;
+      for (int i = 0; i < RPT; ++i) {
+        const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(pan[i][c], tid + NT * i);
+        if (k2 > key) { key = k2; bi = i; }
       }
-    }
-    key = wave_max_u64(key);
-    if (lane == 0) wkey[wid] = key;
-    __syncthreads();
-    unsigned long long best = 0;
+      const unsigned wmax = wave_max_u32(key);
+      if (key == wmax && key != 0) {             // this wavefront's candidate row
 #pragma unroll
-    for (int w = 0; w < NW; ++w) best = wkey[w] > best ? wkey[w] : best;
-    const int r = __builtin_amdgcn_readfirstlane(key_row(best));
-    if (tid == 0) {
-      s_piv[c] = r;
-      const int32_t t0 = G[k];
-      G[k] = G[r];
-      G[r] = t0;
-    }
-    // rows r and k travel through LDS; prow = the new row k
+        for (int i = 0; i < RPT; ++i)
+          if (i == bi) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int row = tid + NT * i;
-      if (row == r) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) prow[cc] = pan[i][cc];
+            for (int cc = 0; cc < NB; ++cc) crow[par][wid][cc] = pan[i][cc];
+          }
       }
-      if (row == k) {
+      if (lane == 0) wkey[par][wid] = wmax;
+      __syncthreads();
+      unsigned best = 0;
+      int bw = 0;
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) srow[cc] = pan[i][cc];
+      for (int w = 0; w < NW; ++w) {
+        const unsigned kw = wkey[par][w];
+        if (kw > best) { best = kw; bw = w; }
       }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int row = tid + NT * i;
-      if (row == r && r != k) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) pan[i][cc] = srow[cc];
+      const int r = __builtin_amdgcn_readfirstlane(key_row(best));
+      bw = __builtin_amdgcn_readfirstlane(bw);
+      const double *prow = crow[par][bw];
+      if (tid == 0) {
+        pivrow[kb + c] = r;
+        stepof[r] = kb + c;
       }
-      if (row == k) {
+      const double piv = prow[c];
+      const bool ok = (piv != 0.0) && isfinite(piv);
+      if (!ok && first_bad == 0) first_bad = isfinite(piv) ? (kb + c + 1) : -(kb + c + 1);
+      const double ip = ok ? 1.0 / piv : 0.0;
+      double sr[NB];
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) pan[i][cc] = prow[cc];
-      }
-    }
-    double piv = 0.0;
+      for (int cc = 0; cc < NB; ++cc) sr[cc] = prow[cc] * ip;
 #pragma unroll
-    for (int cc = 0; cc < NB; ++cc) if (cc == c) piv = prow[cc];
-    const bool ok = (piv != 0.0) && isfinite(piv);
-    if (!ok && first_bad == 0) first_bad = isfinite(piv) ? (k + 1) : -(k + 1);
-    const double ip = ok ? 1.0 / piv : 0.0;
+      for (int i = 0; i < RPT; ++i) {
+        const bool isr = (tid + NT * i == r);
+        if (isr) umask |= 1u << i;
+        const double f = pan[i][c];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int row = tid + NT * i;
-      double f = 0.0;
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) if (cc == c) f = pan[i][cc];
-      if (row == k) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) pan[i][cc] = (cc == c) ? ip : prow[cc] * ip;
-      } else {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc)
-          pan[i][cc] = (cc == c) ? -f * ip : fma(-f, prow[cc] * ip, pan[i][cc]);
+        for (int cc = 0; cc < NB; ++cc) {
+          if (cc == c) pan[i][cc] = isr ? ip : -f * ip;
+          else pan[i][cc] = isr ? sr[cc] : fma(-f, sr[cc], pan[i][cc]);
+        }
       }
     }
   }
   __syncthreads();
-  // write the panel back
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = tid + NT * i;
@@ -597,46 +584,57 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(
         if (c < nbv) A[row + int64_t(kb + c) * n] = pan[i][c];
     }
   }
-  // row interchanges outside the panel: every column on its own, in order
-  for (int j = tid; j < n; j += NT) {
-    if (j >= kb && j < kb + nbv) continue;
-    double *col = A + int64_t(j) * n;
-    for (int c = 0; c < nbv; ++c) {
-      const int k = kb + c, r = s_piv[c];
-      if (r != k) {
-        const double t0 = col[k];
-        col[k] = col[r];
-        col[r] = t0;
-      }
-    }
-  }
-  __syncthreads();
-  // W = pivot rows outside the panel (old values), NB x n, ld NB
-  double *W = (double *)bs.d[BUF_SCR] + d.W;
-  for (int e = tid; e < NB * n; e += NT) {
-    const int c = e % NB, j = e / NB;
-    W[e] = (c < nbv && (j < kb || j >= kb + nbv)) ? A[kb + c + int64_t(j) * n] : 0.0;
-  }
   if (tid == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
 }
 
-// G = identity before the first panel
+// W = the panel's pivot rows outside the panel (old values), NB x m with ld
+// NB, after which those rows of the matrix become 0.  A row of the
+// column-major matrix is a strided gather, so it is spread over a grid of
+// workgroups (one thread per column) rather than done by the panel's single
+// workgroup.
+template <int NB>
+__global__ __launch_bounds__(256) void gj_wgather_kernel(const MergeInvDesc *__restrict__ descs,
+                                                         int nd, int kb, Bases bs,
+                                                         const int32_t *__restrict__ g_all) {
+  const MergeInvDesc &d = descs[blockIdx.y];
+  const int n = d.m;
+  if (kb >= n) return;
+  const int nbv = min(NB, n - kb);
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double *A = (double *)bs.d[BUF_WS] + d.X;
+  double *W = (double *)bs.d[BUF_SCR] + d.W;
+  const int32_t *pivrow = g_all + d.ipiv + kb;
+  const bool inpan = (j >= kb && j < kb + nbv);
+  double *col = A + int64_t(j) * n;
+  double v[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) v[c] = (c < nbv && !inpan) ? col[pivrow[c]] : 0.0;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    W[c + int64_t(j) * NB] = v[c];
+    if (c < nbv && !inpan) col[pivrow[c]] = 0.0;
+  }
+}
+
+// stepof = -1 before the first panel
 __global__ __launch_bounds__(256) void gj_ginit_kernel(const MergeInvDesc *__restrict__ descs,
                                                        int nd, int32_t *__restrict__ g_all) {
   const MergeInvDesc &d = descs[blockIdx.y];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x)
-    g_all[d.ipiv + i] = i;
+    g_all[d.ipiv + d.m + i] = -1;
 }
 
-// Final column interchanges: Y = X (scratch copy), then X(:, G[i]) = Y(:, i).
-__global__ __launch_bounds__(256) void gj_colperm_copy_kernel(
-    const MergeInvDesc *__restrict__ descs, int nd, Bases bs, int to_scratch,
-    const int32_t *__restrict__ g_all) {
+// Inverse from the swept matrix: X[i][j] = M[pivrow[i]][stepof[j]], through a
+// scratch copy Y of M (first pass copies, second gathers).
+__global__ __launch_bounds__(256) void gj_perm_kernel(const MergeInvDesc *__restrict__ descs,
+                                                      int nd, Bases bs, int to_scratch,
+                                                      const int32_t *__restrict__ g_all) {
   const MergeInvDesc &d = descs[blockIdx.y];
   const int n = d.m;
   double *X = (double *)bs.d[BUF_WS] + d.X;
   double *Y = (double *)bs.d[BUF_SCR] + d.W;   // scratch copy (n x n)
-  const int32_t *G = g_all + d.ipiv;
+  const int32_t *pivrow = g_all + d.ipiv, *stepof = pivrow + n;
   const int64_t tot = int64_t(n) * n;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
        e += int64_t(gridDim.x) * blockDim.x) {
@@ -644,7 +642,7 @@ __global__ __launch_bounds__(256) void gj_colperm_copy_kernel(
       Y[e] = X[e];
     } else {
       const int64_t col = e / n, row = e - col * n;
-      X[row + int64_t(G[col]) * n] = Y[e];
+      X[e] = Y[pivrow[row] + int64_t(stepof[col]) * n];
     }
   }
 }
@@ -915,7 +913,13 @@ int panel_nb(int maxm) { (void)maxm; return 16; }
 hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
                            const Bases &bs, int32_t *g, int32_t *info, hipStream_t st) {
   if (nd <= 0) return hipSuccess;
-  if (maxm <= 1024)
+  if (maxm <= 256)
+    hipLaunchKernelGGL((gj_panel_kernel<16, 1, 256>), dim3(nd), dim3(256), 0, st, descs, nd,
+                       kb, bs, g, info);
+  else if (maxm <= 512)
+    hipLaunchKernelGGL((gj_panel_kernel<16, 1, 512>), dim3(nd), dim3(512), 0, st, descs, nd,
+                       kb, bs, g, info);
+  else if (maxm <= 1024)
     hipLaunchKernelGGL((gj_panel_kernel<16, 2, 512>), dim3(nd), dim3(512), 0, st, descs, nd,
                        kb, bs, g, info);
   else if (maxm <= 2048)
@@ -923,6 +927,8 @@ hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
                        kb, bs, g, info);
   else
     return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gj_wgather_kernel<16>), dim3(unsigned((maxm + 255) / 256), nd), dim3(256),
+                     0, st, descs, nd, kb, bs, g);
   return hipGetLastError();
 }
 
@@ -937,9 +943,9 @@ hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const 
                              int32_t *g, int32_t *unused, hipStream_t st) {
   (void)unused;
   if (nd <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gj_colperm_copy_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
+  hipLaunchKernelGGL(gj_perm_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
                      dim3(256), 0, st, descs, nd, bs, 1, g);
-  hipLaunchKernelGGL(gj_colperm_copy_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
+  hipLaunchKernelGGL(gj_perm_kernel, dim3(grid_1d(int64_t(maxm) * maxm, 512), nd),
                      dim3(256), 0, st, descs, nd, bs, 0, g);
   return hipGetLastError();
 }

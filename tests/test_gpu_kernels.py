@@ -50,6 +50,29 @@ def test_inverse_matches_numpy(n):
         assert relerr(X[b], ref) < 1e-10 * np.linalg.cond(A[b]) / n
 
 
+@pytest.mark.parametrize("n", [40, 196, 300, 700])
+def test_inverse_needs_pivoting(n):
+    """One large entry per row and column at random places, the diagonal 0:
+    any pivot choice other than the largest candidate meets a zero or tiny
+    pivot, so this checks the pivot search of both Gauss-Jordan paths."""
+    import torch
+    from paper_1612_02736_amd.hps import debug_invert
+    rng = np.random.default_rng(1000 + n)
+    A = np.zeros((2, n, n))
+    for b in range(2):
+        perm = rng.permutation(n)
+        while np.any(perm == np.arange(n)):
+            perm = rng.permutation(n)
+        A[b] = 1e-3 * rng.standard_normal((n, n))
+        A[b][np.arange(n), np.arange(n)] = 0.0
+        A[b][np.arange(n), perm] = 1.0 + rng.random(n)
+    print(f"invert (pivoting) n={n}", flush=True)
+    X = debug_invert(torch.from_numpy(A).cuda()).cpu().numpy()
+    for b in range(2):
+        ref = np.linalg.inv(A[b])
+        assert relerr(X[b], ref) < 1e-12
+
+
 def _build_pair(nx, ny, p, q=None, refine=None):
     H = _H()
     q = q or p - 1
