@@ -65,6 +65,7 @@ struct Step {
   int kb = 0;
   int64_t fin0 = 0, nfin = 0;  // APPLY: finalize list range
   int64_t fin_maxm = 0;
+  int64_t tmap0 = 0;          // GEMM / APPLY: start of the step's tile map
   bool trans = false;         // APPLY: transposed operator
   // Algorithmic work of the launch: flops (GEMM, Gauss-Jordan, panel) or
   // operator elements read per right-hand side (APPLY).
@@ -96,7 +97,7 @@ struct hps_handle {
   size_t solve_elems = 0;
   // descriptors
   hps::DevArray<hps::GemmDesc> d_gemm;
-  hps::DevArray<int64_t> d_gemm_t0, d_apply_t0;
+  hps::DevArray<int32_t> d_gemm_tmap, d_apply_tmap;   // tile -> descriptor (per step)
   hps::DevArray<hps::LeafDesc> d_leaf;
   hps::DevArray<hps::MergeInvDesc> d_minv;
   hps::DevArray<hps::ApplyDesc> d_apply;
@@ -107,6 +108,7 @@ struct hps_handle {
   // flux-jump residual maps (uniform trees): interior node id, flux index of
   // the west/south leaf and of the east/north leaf
   hps::DevArray<int32_t> d_jn, d_fa, d_fb;
+  int64_t iota_off = 0;            // imap offset of the identity map
   std::vector<int32_t> h_jn, h_fa, h_fb;   // host copies, uploaded by hps_build
   std::vector<double> h_lloc;
   int64_t n_jump = 0;

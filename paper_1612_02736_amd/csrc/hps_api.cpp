@@ -31,7 +31,7 @@ namespace {
 // Host-side descriptor lists of one program, later uploaded.
 struct GemmList {
   std::vector<GemmDesc> d;
-  std::vector<int64_t> t0;
+  std::vector<int32_t> tmap;   // owning descriptor of each tile (index into d)
   int64_t tiles = 0;
   void add(const GemmDesc &g0) {
     GemmDesc g = g0;
@@ -39,8 +39,8 @@ struct GemmList {
     const int64_t tm = (g.M + 63) / 64;
     if (g.M <= 0 || g.N <= 0) return;
     g.tile0 = tiles;
-    t0.push_back(tiles);
     tiles += tm * g.tn;
+    tmap.insert(tmap.end(), size_t(tm * g.tn), int32_t(d.size()));
     d.push_back(g);
   }
 };
@@ -278,8 +278,9 @@ void gemm_step(GemmList &gl, GemmList &tmp, std::vector<Step> &prog) {
   s.d0 = (int64_t)gl.d.size();
   s.nd = (int64_t)tmp.d.size();
   s.ntiles = tmp.tiles;
+  s.tmap0 = (int64_t)gl.tmap.size();
   for (auto &g : tmp.d) gl.d.push_back(g);
-  for (auto t : tmp.t0) gl.t0.push_back(t);
+  gl.tmap.insert(gl.tmap.end(), tmp.tmap.begin(), tmp.tmap.end());   // relative to d0
   prog.push_back(s);
 }
 
@@ -349,7 +350,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
                        std::vector<std::pair<int64_t, std::vector<double>>> &ws_blocks,
                        std::vector<int32_t> &imap, GemmList &gl, std::vector<LeafDesc> &leafd,
                        std::vector<MergeInvDesc> &minv, std::vector<ApplyDesc> &appl,
-                       std::vector<int64_t> &appl_t0, std::vector<int32_t> &finlist,
+                       std::vector<int32_t> &appl_tmap, std::vector<int32_t> &finlist,
                        std::vector<VecOpDesc> &vops) {
   Plan &pl = H->pl;
   const int p = H->p, q = H->q, mi = H->mi, me = H->me, g4 = H->g4;
@@ -695,16 +696,24 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     Step s{S_APPLY};
     s.d0 = (int64_t)appl.size();
     s.nd = (int64_t)tmp.size();
+    s.tmap0 = (int64_t)appl_tmap.size();
     int64_t tiles = 0;
     s.fin0 = (int64_t)finlist.size();
+    // k-slices: at most 512 k per tile, and enough tiles in the launch to
+    // fill the chip (about 1024 workgroups), with at least 64 k per slice
+    int64_t sum_rb = 0;
+    for (auto &a : tmp) sum_rb += (a.M + 63) / 64;
+    const int want = int(std::max<int64_t>(1, (1024 + sum_rb - 1) / std::max<int64_t>(1, sum_rb)));
     for (auto &a : tmp) {
       const int K = a.K1 + (a.mode == 0 ? a.K2 : 0);
       a.rb = (a.M + 63) / 64;
       a.ksl = std::max(1, std::min(64, (K + 511) / 512));
-      if (int64_t(a.rb) * a.ksl < 4 && K >= 256) a.ksl = std::max(a.ksl, std::min(8, K / 128));
+      a.ksl = std::max(a.ksl, std::min(want, std::max(1, K / 64)));
+      a.ksl = std::min(a.ksl, 64);
       a.tile0 = tiles;
-      appl_t0.push_back(tiles);
       tiles += int64_t(a.rb) * a.ksl;
+      appl_tmap.insert(appl_tmap.end(), size_t(int64_t(a.rb) * a.ksl),
+                       int32_t(appl.size() - s.d0));
       if (a.ksl > 1) {
         a.part = part_off;
         part_off += int64_t(a.ksl) * a.M;
@@ -1076,6 +1085,12 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   }
   H->part_per_rhs = part_off;
   H->off_T = Lo.T; H->off_X = Lo.X; H->off_S = Lo.S; H->off_LD = Lo.LD; H->off_H = Lo.H;
+  // identity map covering every k an apply reads from an unmapped operand
+  int maxk = 1;
+  for (const ApplyDesc &a : appl) maxk = std::max(maxk, std::max(a.K1, a.K2));
+  std::vector<int32_t> iota(maxk);
+  for (int k = 0; k < maxk; ++k) iota[k] = k;
+  H->iota_off = imap_put(iota);
   return HPS_OK;
 }
 
@@ -1087,6 +1102,7 @@ Bases make_bases(hps_handle *H) {
   b.d[BUF_W32] = H->ws32.p;
   b.d[BUF_AUX] = H->aux.p;
   b.imap = H->imap.p;
+  b.iota = H->imap.p ? H->imap.p + H->iota_off : nullptr;
   return b;
 }
 
@@ -1137,7 +1153,7 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
     }
     switch (s.kind) {
       case S_GEMM:
-        e = launch_gemm(H->d_gemm.p + s.d0, H->d_gemm_t0.p + s.d0, (int)s.nd, s.ntiles, bs, st);
+        e = launch_gemm(H->d_gemm.p + s.d0, H->d_gemm_tmap.p + s.tmap0, s.ntiles, bs, st);
         break;
       case S_GJ_LEAF:
         e = launch_gj_leaf(H->p, H->d_leaf.p + s.d0, (int)s.nd, bs, H->aux.p + H->Dh_off,
@@ -1159,7 +1175,7 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
                               st);
         break;
       case S_APPLY:
-        e = launch_apply(prec, H->d_apply.p + s.d0, H->d_apply_t0.p + s.d0, (int)s.nd, s.ntiles,
+        e = launch_apply(prec, H->d_apply.p + s.d0, H->d_apply_tmap.p + s.tmap0, s.ntiles,
                          bs, nrhs, st, s.trans);
         if (e == hipSuccess && s.nfin > 0)
           e = launch_apply_finalize(H->d_apply.p, H->d_finlist.p + s.fin0, (int)s.nfin,
@@ -1201,7 +1217,7 @@ size_t hps_build_workspace_size(const hps_tree *tree, int p, int q) {
   std::vector<LeafDesc> ld;
   std::vector<MergeInvDesc> mv;
   std::vector<ApplyDesc> ap;
-  std::vector<int64_t> at0;
+  std::vector<int32_t> at0;
   std::vector<int32_t> fl;
   std::vector<VecOpDesc> vo;
   if (plan_handle(&H, Lo, wi, blocks, imap, gl, ld, mv, ap, at0, fl, vo)) return 0;
@@ -1235,10 +1251,10 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   std::vector<LeafDesc> leafd;
   std::vector<MergeInvDesc> minv;
   std::vector<ApplyDesc> appl;
-  std::vector<int64_t> appl_t0;
+  std::vector<int32_t> appl_tmap;
   std::vector<int32_t> finlist;
   std::vector<VecOpDesc> vops;
-  rc = plan_handle(H.get(), Lo, aux_init, blocks, imap, gl, leafd, minv, appl, appl_t0, finlist,
+  rc = plan_handle(H.get(), Lo, aux_init, blocks, imap, gl, leafd, minv, appl, appl_tmap, finlist,
                    vops);
   if (rc) return rc;
   for (auto *prog : {&H->build_prog, &H->up_prog, &H->down_prog, &H->adj_down_prog,
@@ -1258,11 +1274,11 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
     HIPCHK(hipMemcpy(H->ws.p + bl.first, bl.second.data(), bl.second.size() * sizeof(double),
                      hipMemcpyHostToDevice));
   HIPCHK(H->d_gemm.upload(gl.d));
-  HIPCHK(H->d_gemm_t0.upload(gl.t0));
+  HIPCHK(H->d_gemm_tmap.upload(gl.tmap));
   HIPCHK(H->d_leaf.upload(leafd));
   HIPCHK(H->d_minv.upload(minv));
   HIPCHK(H->d_apply.upload(appl));
-  HIPCHK(H->d_apply_t0.upload(appl_t0));
+  HIPCHK(H->d_apply_tmap.upload(appl_tmap));
   HIPCHK(H->d_finlist.upload(finlist));
   HIPCHK(H->d_vecop.upload(vops));
   HIPCHK(H->d_jn.upload(H->h_jn));
@@ -1406,12 +1422,12 @@ extern "C" int hps_debug_gemm(int M, int N, int K, double alpha, const double *A
   g.D = noref(); g.crow = g.ccol = -1; g.alpha = alpha; g.beta = 0.0;
   gl.add(g);
   DevArray<GemmDesc> dd;
-  DevArray<int64_t> dt;
+  DevArray<int32_t> dt;
   HIPCHK(dd.upload(gl.d));
-  HIPCHK(dt.upload(gl.t0));
+  HIPCHK(dt.upload(gl.tmap));
   Bases bs{};
   bs.d[BUF_IN0] = (void *)A; bs.d[BUF_IN1] = (void *)B; bs.d[BUF_IN2] = (void *)C;
-  HIPCHK(launch_gemm(dd.p, dt.p, 1, gl.tiles, bs, st));
+  HIPCHK(launch_gemm(dd.p, dt.p, gl.tiles, bs, st));
   HIPCHK(hipStreamSynchronize(st));
   return HPS_OK;
 }
@@ -1444,7 +1460,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   emit_inverse_steps(lev, minv, gl, prog);
   HIPCHK(H.d_minv.upload(minv));
   HIPCHK(H.d_gemm.upload(gl.d));
-  HIPCHK(H.d_gemm_t0.upload(gl.t0));
+  HIPCHK(H.d_gemm_tmap.upload(gl.tmap));
   Bases bs = make_bases(&H);
   int rc = run_prog(&H, prog, bs, 1, 0, st);
   if (rc) return rc;

@@ -25,16 +25,6 @@ namespace hps {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int find_desc_tile0(const int64_t *tile0s, int n,
-                                               int64_t tile) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (tile0s[mid] <= tile) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Tiles handed out so that the blocks one XCD receives (block b runs on XCD
 // b % 8) form a contiguous run of logical tiles: neighbouring tiles share
@@ -85,13 +75,13 @@ constexpr int GBM = 64, GBN = 64, GBK = 32;
 // tiles), K in steps of 32: the next A/B tiles are fetched into registers
 // while the MFMAs run on the current tiles in LDS.
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
-    const GemmDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
-    int ndesc, int64_t ntiles, Bases bs) {
+    const GemmDesc *__restrict__ descs, const int32_t *__restrict__ tmap,
+    int64_t ntiles, Bases bs) {
   __shared__ double As[GBK][GBM + 1];
   __shared__ double Bs[GBK][GBN + 1];
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
-  const GemmDesc &d = descs[find_desc_tile0(tile0s, ndesc, tile)];
+  const GemmDesc &d = descs[tmap[tile]];
   const int64_t t = tile - d.tile0;
   const int row0 = int(t / d.tn) * GBM, col0 = int(t % d.tn) * GBN;
   const int M = d.M, N = d.N, K = d.K;
@@ -666,15 +656,15 @@ __device__ __forceinline__ double vload(const Bases &bs, const VRef &v, int64_t 
 
 template <typename TA, typename TC_, int NR, bool TRANS>
 __global__ __launch_bounds__(256) void apply_kernel(
-    const ApplyDesc *__restrict__ descs, const int64_t *__restrict__ tile0s,
-    int ndesc, int64_t ntiles, Bases bs, int nrhs) {
+    const ApplyDesc *__restrict__ descs, const int32_t *__restrict__ tmap,
+    int64_t ntiles, Bases bs, int nrhs) {
   constexpr int KC = NR >= 16 ? 64 : 256;
   constexpr int RC = NR < 8 ? NR : 8;     // RHS per cross-wave reduction round
   __shared__ TC_ Bsh[KC][NR];
   __shared__ TC_ red[4][64][RC];
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
-  const ApplyDesc &d = descs[find_desc_tile0(tile0s, ndesc, tile)];
+  const ApplyDesc &d = descs[tmap[tile]];
   const int64_t t = tile - d.tile0;
   const int rbi = int(t % d.rb), slice = int(t / d.rb);
   const int K = d.K1 + (d.mode == 0 ? d.K2 : 0);
@@ -755,6 +745,222 @@ __global__ __launch_bounds__(256) void apply_kernel(
   }
 }
 
+// A vector operand resolved once per workgroup: element (k, r) is
+// b[map[k] * kmul + r * rstep], where b already includes the operand's offset
+// (interleaved: kmul = nrhs, rstep = 1; RHS-major: kmul = 1, rstep = stride)
+// and an unmapped operand reads the identity map.
+struct VSrc {
+  const double *b;
+  const int32_t *map;
+  int32_t kmul, rstep;
+};
+__device__ __forceinline__ VSrc vsrc(const Bases &bs, const VRef &v, int nrhs) {
+  VSrc s;
+  const bool il = v.stride < 0;
+  s.b = v.buf >= 0 ? (const double *)bs.d[v.buf] + (il ? v.off * nrhs : v.off) : nullptr;
+  s.map = v.map >= 0 ? bs.imap + v.map : bs.iota;
+  s.kmul = il ? nrhs : 1;
+  s.rstep = il ? 1 : int32_t(v.stride);
+  return s;
+}
+
+
+// Right operand entries (kc + kk, r0 + r) of one k chunk into registers:
+// entry j of thread tid is (kk, r) = (tid % KC, tid / KC + (256 / KC) j) when
+// kfast, else (tid / NR + (256 / NR) j, tid % NR).  The gather indices of
+// the tile's k range are in LDS (ixs, read once per tile), so a chunk costs
+// one memory round trip.  Entries past the chunk or past nrhs read a valid
+// element and are zeroed.
+template <int NR, int KC>
+__device__ __forceinline__ void stage_regs(double (&breg)[KC * NR / 256], int mode, int K1,
+                                           const VSrc &s1, const VSrc &s2, const VSrc &s3,
+                                           const int (*ixs)[512], int k0, int kc, int kn,
+                                           int r0, int nrhs, int tid, bool kfast) {
+  constexpr int NB = KC * NR / 256;
+  const int kk0 = kfast ? tid % KC : tid / NR, r00 = kfast ? tid / KC : tid % NR;
+  int kx[NB], rx[NB];
+  bool ok[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int kk = kfast ? kk0 : kk0 + (256 / NR) * j;
+    const int r = kfast ? r00 + (256 / KC) * j : r00;
+    ok[j] = kk < kn && r0 + r < nrhs;
+    kx[j] = ok[j] ? kc + kk : kc;
+    rx[j] = ok[j] ? r0 + r : r0;
+  }
+  if (mode == 0) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const bool in2 = kx[j] >= K1;
+      const double *b = in2 ? s2.b : s1.b;
+      const int64_t o = int64_t(ixs[0][kx[j] - k0]) * (in2 ? s2.kmul : s1.kmul) +
+                        int64_t(rx[j]) * (in2 ? s2.rstep : s1.rstep);
+      breg[j] = b[o];
+    }
+  } else {
+    const bool has3 = mode == 1 && s3.b;
+    double va[NB], vb[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      va[j] = s1.b[int64_t(ixs[0][kx[j] - k0]) * s1.kmul + int64_t(rx[j]) * s1.rstep];
+      vb[j] = s2.b[int64_t(ixs[1][kx[j] - k0]) * s2.kmul + int64_t(rx[j]) * s2.rstep];
+    }
+    if (has3) {
+      double vc[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        vc[j] = s3.b[int64_t(ixs[2][kx[j] - k0]) * s3.kmul + int64_t(rx[j]) * s3.rstep];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) breg[j] = va[j] - vb[j] + vc[j];
+    } else if (mode == 2) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) breg[j] = va[j] + vb[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) breg[j] = va[j] - vb[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    if (!ok[j]) breg[j] = 0.0;
+}
+
+// FP64 apply on the matrix cores for 16 or more right-hand sides: the same
+// tiles (64 operator rows x one k-slice) as apply_kernel, with the 64 rows
+// split over the four wavefronts (16 each) and 16 x 16 x 4 MFMA steps over
+// k, so no cross-wavefront reduction is needed.  NT16 = right-hand-side
+// tiles of 16 per workgroup.  f64 MFMA operand layouts: lane l holds
+// A(l % 16, l / 16) and B(l / 16, l % 16); the result register v of lane l is
+// C((l >> 4) + 4 v, l & 15).
+//
+// Software pipeline over k chunks of KC: the operator entries and the right
+// operand of chunk c + 1 are loaded into registers while chunk c runs on the
+// matrix cores; the right operand goes through a double-buffered LDS tile, so
+// one barrier per chunk suffices.  The right operand is read along its
+// contiguous direction (k for RHS-major arrays, right-hand sides otherwise).
+template <int NT16, bool TRANS>
+__global__ __launch_bounds__(256) void apply_mfma_kernel(
+    const ApplyDesc *__restrict__ descs, const int32_t *__restrict__ tmap,
+    int64_t ntiles, Bases bs, int nrhs) {
+  constexpr int NR = 16 * NT16;
+  constexpr int KC = 64;
+  constexpr int NB = KC * NR / 256;          // right-operand entries per thread
+  __shared__ double Bsh[2][KC][NR + 1];
+  __shared__ int ixs[3][512];               // gather indices of the tile's k range
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= ntiles) return;
+  const ApplyDesc &d = descs[tmap[tile]];
+  const int64_t t = tile - d.tile0;
+  const int rbi = int(t % d.rb), slice = int(t / d.rb);
+  const int K = d.K1 + (d.mode == 0 ? d.K2 : 0);
+  const int kper = (K + d.ksl - 1) / d.ksl;
+  const int k0 = slice * kper, k1 = min(K, k0 + kper);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r0 = blockIdx.y * NR;
+  const double *A = (const double *)bs.d[d.abuf] + d.aoff;
+  const int lda = d.lda;
+  const int arow = rbi * 64 + wid * 16 + (lane & 15);   // operand row of this lane
+  const bool arow_ok = arow < d.M;
+  const int kl = lane >> 4;
+  dbl4 acc[NT16];
+#pragma unroll
+  for (int u = 0; u < NT16; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double abuf[KC / 4], breg[NB];
+  const int mode = d.mode, K1 = d.K1;
+  const VSrc s1 = vsrc(bs, d.B1, nrhs), s2 = vsrc(bs, d.B2, nrhs), s3 = vsrc(bs, d.B3, nrhs);
+  for (int k = k0 + tid; k < k1; k += 256) {
+    if (mode == 0) {
+      ixs[0][k - k0] = k < K1 ? s1.map[k] : s2.map[k - K1];
+    } else {
+      ixs[0][k - k0] = s1.map[k];
+      ixs[1][k - k0] = s2.map[k];
+      if (s3.b) ixs[2][k - k0] = s3.map[k];
+    }
+  }
+  __syncthreads();
+  // operator entries of chunk kc: abuf[j] = A(arow, kc + 4 j + kl)
+#define HPS_LOAD_CHUNK(KCV, KF)                                                             \
+  {                                                                                         \
+    const int kn_ = min(KC, k1 - (KCV));                                                    \
+    _Pragma("unroll") for (int j = 0; j < KC / 4; ++j) {                                    \
+      const int kk = 4 * j + kl;                                                            \
+      abuf[j] = (arow_ok && kk < kn_)                                                       \
+                    ? (TRANS ? A[int64_t(arow) * lda + (KCV) + kk]                          \
+                             : A[arow + int64_t((KCV) + kk) * lda])                         \
+                    : 0.0;                                                                  \
+    }                                                                                       \
+    const int kmid = (KCV) + min(kn_ - 1, KC / 2);                                          \
+    KF = ((mode == 0 && kmid >= K1) ? s2.kmul : s1.kmul) == 1;                              \
+    stage_regs<NR, KC>(breg, mode, K1, s1, s2, s3, ixs, k0, (KCV), kn_, r0, nrhs, tid, KF); \
+  }
+  bool kfast = false;
+  if (k0 < k1) HPS_LOAD_CHUNK(k0, kfast);
+  int buf = 0;
+  for (int kc = k0; kc < k1; kc += KC) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int kk = kfast ? tid % KC : tid / NR + (256 / NR) * j;
+      const int r = kfast ? tid / KC + (256 / KC) * j : tid % NR;
+      Bsh[buf][kk][r] = breg[j];
+    }
+    double acur[KC / 4];
+#pragma unroll
+    for (int j = 0; j < KC / 4; ++j) acur[j] = abuf[j];
+    __syncthreads();
+    if (kc + KC < k1) HPS_LOAD_CHUNK(kc + KC, kfast);
+#pragma unroll
+    for (int j = 0; j < KC / 4; ++j) {
+      const int kk = 4 * j + kl;
+#pragma unroll
+      for (int u = 0; u < NT16; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[j], Bsh[buf][kk][16 * u + (lane & 15)],
+                                                      acc[u], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+#undef HPS_LOAD_CHUNK
+  if (d.ksl == 1 && d.C.stride < 0) {
+    // interleaved result: the MFMA layout (lanes along right-hand sides) is
+    // already contiguous
+#pragma unroll
+    for (int u = 0; u < NT16; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rbi * 64 + wid * 16 + (lane >> 4) + 4 * v;
+        const int rg = r0 + 16 * u + (lane & 15);
+        if (row >= d.M || rg >= nrhs) continue;
+        double val = d.alpha * acc[u][v];
+        if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
+        *vaddr(bs, d.C, row, rg, nrhs) = val;
+      }
+    return;
+  }
+  // RHS-major result or split-K partials: transpose through LDS so that
+  // lanes run along rows (buffer `buf` was last read two chunks ago)
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NT16; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      Bsh[buf][wid * 16 + (lane >> 4) + 4 * v][16 * u + (lane & 15)] = acc[u][v];
+  __syncthreads();
+  const int row = rbi * 64 + lane;
+  if (row >= d.M) return;
+#pragma unroll
+  for (int j = 0; j < NR / 4; ++j) {
+    const int r = wid + 4 * j, rg = r0 + r;
+    if (rg >= nrhs) continue;
+    const double sv = Bsh[buf][lane][r];
+    if (d.ksl == 1) {
+      double val = d.alpha * sv;
+      if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
+      *vaddr(bs, d.C, row, rg, nrhs) = val;
+    } else {
+      ((double *)bs.d[BUF_SCR])[d.part * nrhs + (int64_t(slice) * nrhs + rg) * d.M + row] = sv;
+    }
+  }
+}
+
 // Sum the split-K partials of each descriptor in slice order.
 __global__ __launch_bounds__(256) void apply_finalize_kernel(
     const ApplyDesc *__restrict__ descs, const int32_t *__restrict__ list, int nlist,
@@ -823,12 +1029,12 @@ static inline unsigned grid_1d(int64_t n, int64_t cap = 65536) {
   return unsigned(b);
 }
 
-hipError_t launch_gemm(const GemmDesc *descs, const int64_t *tile0s, int ndesc,
-                       int64_t ntiles, const Bases &bs, hipStream_t st) {
+hipError_t launch_gemm(const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
+                       const Bases &bs, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   const int64_t nblk = (ntiles + 7) / 8 * 8;
   hipLaunchKernelGGL(gemm_f64_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, descs,
-                     tile0s, ndesc, ntiles, bs);
+                     tmap, ntiles, bs);
   return hipGetLastError();
 }
 
@@ -951,13 +1157,13 @@ hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const 
 }
 
 template <typename TA, typename TC_, bool TRANS>
-static void launch_apply_t(const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
+static void launch_apply_t(const ApplyDesc *descs, const int32_t *tmap,
                            int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st) {
   const int64_t nblk = (ntiles + 7) / 8 * 8;
 #define HPS_APPLY_NR(NRV)                                                                  \
   hipLaunchKernelGGL((apply_kernel<TA, TC_, NRV, TRANS>),                                 \
                      dim3(unsigned(nblk), unsigned((nrhs + NRV - 1) / NRV)), dim3(256), 0, st, \
-                     descs, tile0s, ndesc, ntiles, bs, nrhs)
+                     descs, tmap, ntiles, bs, nrhs)
   if (nrhs > 16) HPS_APPLY_NR(32);
   else if (nrhs > 8) HPS_APPLY_NR(16);
   else if (nrhs > 4) HPS_APPLY_NR(8);
@@ -967,19 +1173,34 @@ static void launch_apply_t(const ApplyDesc *descs, const int64_t *tile0s, int nd
 #undef HPS_APPLY_NR
 }
 
-hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
+hipError_t launch_apply(int prec, const ApplyDesc *descs, const int32_t *tmap,
                         int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st, bool trans) {
   if (ntiles <= 0) return hipSuccess;
+  if (prec == 0 && nrhs >= 16) {
+    const int64_t nblk = (ntiles + 7) / 8 * 8;
+    const bool two = nrhs > 16;
+    const unsigned gy = unsigned((nrhs + (two ? 31 : 15)) / (two ? 32 : 16));
+#define HPS_APPLY_MFMA(NT, TR)                                                             \
+  hipLaunchKernelGGL((apply_mfma_kernel<NT, TR>), dim3(unsigned(nblk), gy), dim3(256), 0, st, \
+                     descs, tmap, ntiles, bs, nrhs)
+    if (two) {
+      if (trans) HPS_APPLY_MFMA(2, true); else HPS_APPLY_MFMA(2, false);
+    } else {
+      if (trans) HPS_APPLY_MFMA(1, true); else HPS_APPLY_MFMA(1, false);
+    }
+#undef HPS_APPLY_MFMA
+    return hipGetLastError();
+  }
   if (trans) {
     if (prec == 0)
-      launch_apply_t<double, double, true>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+      launch_apply_t<double, double, true>(descs, tmap, ntiles, bs, nrhs, st);
     else
-      launch_apply_t<float, float, true>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+      launch_apply_t<float, float, true>(descs, tmap, ntiles, bs, nrhs, st);
   } else {
     if (prec == 0)
-      launch_apply_t<double, double, false>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+      launch_apply_t<double, double, false>(descs, tmap, ntiles, bs, nrhs, st);
     else
-      launch_apply_t<float, float, false>(descs, tile0s, ndesc, ntiles, bs, nrhs, st);
+      launch_apply_t<float, float, false>(descs, tmap, ntiles, bs, nrhs, st);
   }
   return hipGetLastError();
 }

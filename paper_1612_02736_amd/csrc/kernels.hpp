@@ -12,8 +12,9 @@ namespace hps {
 constexpr int kPanelNBMax = 32;   // widest panel of the blocked Gauss-Jordan
 int panel_nb(int maxm);           // panel width used for a level of size maxm
 
-hipError_t launch_gemm(const GemmDesc *descs, const int64_t *tile0s, int ndesc,
-                       int64_t ntiles, const Bases &bs, hipStream_t st);
+// tmap[t] = index (into descs) of the descriptor that owns tile t
+hipError_t launch_gemm(const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
+                       const Bases &bs, hipStream_t st);
 int gj_leaf_supported(int p);
 hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
                           const double *Dh, const double *Dh2, const int32_t *ice,
@@ -29,7 +30,7 @@ hipError_t launch_gj_ginit(const MergeInvDesc *descs, int nd, int maxm, int32_t 
                            hipStream_t st);
 hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
                              int32_t *ipiv, int32_t *src, hipStream_t st);
-hipError_t launch_apply(int prec, const ApplyDesc *descs, const int64_t *tile0s, int ndesc,
+hipError_t launch_apply(int prec, const ApplyDesc *descs, const int32_t *tmap,
                         int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st,
                         bool trans = false);
 hipError_t launch_apply_finalize(const ApplyDesc *descs, const int32_t *list, int nlist,

@@ -23,6 +23,7 @@ enum BufId : int32_t {
 struct Bases {
   void *d[NBUF];
   const int32_t *imap;  // integer maps (gather/scatter lists)
+  const int32_t *iota;  // iota[k] = k for every k an apply reads (unmapped operands)
 };
 
 struct Ref {

@@ -96,18 +96,28 @@ def test_adjoint_matches_oracle(n, p, refine, nprob):
         assert relerr(gb[r], go) <= 1e-11, ("gbar", r)
 
 
-def test_adjoint_dot_product_identity():
+@pytest.mark.parametrize("nrhs", [3, 18])
+def test_adjoint_dot_product_identity(nrhs):
+    """<u, y> = <f, fbar> + <g, gbar> for u = solve(f, g) and (fbar, gbar) =
+    adjoint(y); 18 right-hand sides take the MFMA apply path both ways."""
     H, s, ops, t, p, q, f, g = _adjoint_pair(4, 12)
     rng = np.random.default_rng(8)
     nl, nb = t.n_leaves, t.counts(q)[1]
-    f1 = rng.standard_normal((3, nb))
-    g1 = rng.standard_normal((3, nl, (p - 2) ** 2))
-    y = rng.standard_normal((3, nl, p * p))
+    f1 = rng.standard_normal((nrhs, nb))
+    g1 = rng.standard_normal((nrhs, nl, (p - 2) ** 2))
+    y = rng.standard_normal((nrhs, nl, p * p))
     u = s.solve(to_dev(f1), to_dev(g1)).cpu().numpy()
     fb, gb = s.solve_adjoint(to_dev(y))
-    lhs = np.sum(u * y)
-    rhs = np.sum(f1 * fb.cpu().numpy()) + np.sum(g1 * gb.cpu().numpy())
-    assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(u * y))
+    fb, gb = fb.cpu().numpy(), gb.cpu().numpy()
+    for r in range(nrhs):
+        lhs = np.sum(u[r] * y[r])
+        rhs = np.sum(f1[r] * fb[r]) + np.sum(g1[r] * gb[r])
+        assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(u[r] * y[r])), r
+    if nrhs > 16:
+        for r in (0, nrhs - 1):
+            fo, go = oracle.solve_adjoint(ops, y[r])
+            assert relerr(fb[r], fo) <= 1e-11, ("fbar", r)
+            assert relerr(gb[r], go) <= 1e-11, ("gbar", r)
 
 
 def test_coefficient_gradient_finite_differences():

@@ -106,6 +106,32 @@ def test_multiple_rhs(nrhs):
         assert relerr(u[r], uo) <= TOL, r
 
 
+@pytest.mark.parametrize("nrhs", [16, 20, 32])
+def test_many_rhs_matrix_core_path(nrhs):
+    """16 or more right-hand sides take the MFMA apply path: every column
+    agrees with the single-right-hand-side solve (the vector path) and two
+    of them with the oracle."""
+    H = _lib()
+    p, q = 12, 11
+    t = H.Tree(0, 1, 0, 1, 4, 4)
+    ot = oracle.Tree.uniform(0, 1, 0, 1, 4, 4)
+    sols = [W.FourierSolution(40 + r) for r in range(nrhs)]
+    fs, gs = [], []
+    for sol in sols:
+        coeffs, f, g, _ = lib_inputs(t, p, q, W.varcoeff, sol)
+        fs.append(f)
+        gs.append(g)
+    s = H.Solver(t, to_dev(coeffs), p, q)
+    F, G = np.stack(fs), np.stack(gs)
+    u = s.solve(to_dev(F), to_dev(G)).cpu().numpy()
+    for r in range(nrhs):
+        u1 = s.solve(to_dev(F[r:r + 1]), to_dev(G[r:r + 1]))[0].cpu().numpy()
+        assert relerr(u[r], u1) <= 1e-13, r
+    for r in (0, nrhs - 1):
+        uo, _ = oracle_solution(ot, p, q, W.varcoeff, sols[r])
+        assert relerr(u[r], uo) <= TOL, r
+
+
 def test_polynomial_reproduction_full_size_64x64():
     """A solution of tensor degree <= q-1 is reproduced to roundoff on any
     tree for the full variable-coefficient operator.  Roundoff grows with the
