@@ -134,8 +134,13 @@ struct hps_handle {
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
   std::unique_ptr<hps::SolveExt, hps::SolveExtDeleter> ext;
+  // refactorization replays the build program as one HIP graph, captured on
+  // the first refactor (and again if the scratch buffer has moved)
+  hipGraphExec_t build_exec = nullptr;
+  const void *build_exec_scr = nullptr;
   ~hps_handle() {
     for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
-  }    // residual / refinement / adjoint data
+    if (build_exec) (void)hipGraphExecDestroy(build_exec);
+  }
 };
 

@@ -1326,9 +1326,35 @@ int hps_refactor(hps_handle *H, const double *coeffs, void *stream) {
   const size_t ncoef = size_t(H->nleaf) * 6 * H->p * H->p;
   HIPCHK(hipMemcpyAsync(H->coef.p, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, st));
   Bases bs = make_bases(H);
-  bs.d[BUF_IN0] = (void *)coeffs;
-  int rc = run_prog(H, H->build_prog, bs, 1, 0, st);
-  if (rc) return rc;
+  bs.d[BUF_IN0] = H->coef.p;          // the handle's copy: fixed address for the graph
+  int rc = HPS_OK;
+  if (H->prof_on) {
+    rc = run_prog(H, H->build_prog, bs, 1, 0, st);   // per-launch events need eager launches
+  } else {
+    if (!H->build_exec || H->build_exec_scr != H->scr.p) {
+      if (H->build_exec) HIPCHK(hipGraphExecDestroy(H->build_exec));
+      H->build_exec = nullptr;
+      hipStream_t cs;
+      HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        rc = run_prog(H, H->build_prog, bs, 1, 0, cs);
+        e = hipStreamEndCapture(cs, &g);
+      }
+      if (e == hipSuccess && rc == HPS_OK)
+        e = hipGraphInstantiate(&H->build_exec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      if (rc) return rc;
+      if (e != hipSuccess) {
+        H->build_exec = nullptr;
+        return fail(HPS_EHIP, std::string("build graph: ") + hipGetErrorString(e));
+      }
+      H->build_exec_scr = H->scr.p;
+    }
+    HIPCHK(hipGraphLaunch(H->build_exec, st));
+  }
   std::vector<int32_t> info(H->n_info);
   HIPCHK(hipMemcpyAsync(info.data(), H->info.p, sizeof(int32_t) * H->n_info,
                         hipMemcpyDeviceToHost, st));

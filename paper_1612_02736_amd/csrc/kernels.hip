@@ -415,6 +415,212 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
   if (tid == 0) info[d.info] = sh.info;
 }
 
+// ---------------------------------------------------------------------------
+// Column-owner Gauss-Jordan (one barrier per step)
+// ---------------------------------------------------------------------------
+// NW wavefronts; lane l owns rows l + 64 i (i < RA) and wavefront w owns
+// columns w + NW b (b < CB), so a whole column lives in one wavefront.  Step
+// k = NW b + w eliminates column k, held in slot b of wavefront w; the loop
+// over b is unrolled so that slot is a compile-time constant.  The owner of
+// column k has searched its pivot with a wavefront reduction and published
+// the column (pivot row entry set to 0), the pivot row index and the pivot
+// value in LDS; every wavefront reads its part of the pivot row from its own
+// registers (readlane of lane r mod 64) and applies the rank-1 update, the
+// owner of column k + 1 updating and publishing that column before its
+// others.  One barrier per step.  Pivot rows stay unscaled as in gj_core.
+template <int NW, int RA>
+struct GJ2Shared {
+  double fbuf[2][64 * RA];   // published pivot column (pivot row entry 0)
+  double piv[2];
+  int rsel[2];
+  double sig[64 * RA];       // 1 / pivot of step k
+  int pivrow[64 * RA];
+  int stepof[64 * RA];
+  int info;
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(unsigned(b)), l);
+  const unsigned hi = __builtin_amdgcn_readlane(int(unsigned(b >> 32)), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Owner wavefront of column k (in its slot `slot`, a compile-time constant
+// after unrolling): pivot search over the unused rows, then publish column,
+// pivot row and pivot value for step k.
+template <int NW, int RA, int CB>
+__device__ __forceinline__ void gj2_publish(const double (&a)[RA][CB], unsigned umask, int slot,
+                                            int k, int lane, GJ2Shared<NW, RA> &sh) {
+  double x[RA];
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    x[i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) if (c == slot) x[i] = a[i][c];
+  }
+  unsigned key = 0;
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(x[i], 64 * i);
+    key = k2 > key ? k2 : key;
+  }
+  if (key) key -= unsigned(lane);
+  const unsigned wmax = wave_max_u32(key);
+  const int r = __builtin_amdgcn_readfirstlane(key_row(wmax));
+  const int ir = r >> 6, rl = r & 63;
+  const int par = k & 1;
+  double pv = 0.0;
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    sh.fbuf[par][lane + 64 * i] = (lane + 64 * i == r) ? 0.0 : x[i];
+    if (i == ir) pv = readlane_f64(x[i], rl);
+  }
+  if (lane == 0) {
+    sh.piv[par] = pv;
+    sh.rsel[par] = r;
+    sh.pivrow[k] = r;
+    sh.stepof[r] = k;
+    const bool ok = (pv != 0.0) && isfinite(pv);
+    sh.sig[k] = ok ? 1.0 / pv : 0.0;
+    if (!ok && sh.info == 0) sh.info = isfinite(pv) ? (k + 1) : -(k + 1);
+  }
+}
+
+template <int RA, int CB>
+__device__ __forceinline__ void gj2_pivot_row(const double (&a)[RA][CB], int ir, int rl,
+                                              double (&s)[CB]) {
+#pragma unroll
+  for (int i = 0; i < RA; ++i)
+    if (i == ir) {
+#pragma unroll
+      for (int b = 0; b < CB; ++b) s[b] = readlane_f64(a[i][b], rl);
+    }
+}
+
+// Steps k = NW B + kk (kk < NW) for register slot B, then the next slot
+// (template recursion keeps every slot index a compile-time constant).
+template <int NW, int RA, int CB, int B>
+__device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, const int lane,
+                                          const int wid, unsigned &umask, GJ2Shared<NW, RA> &sh) {
+  if constexpr (B < CB) {
+    const int kend = min(NW, n - B * NW);
+    for (int kk = 0; kk < kend; ++kk) {
+      const int k = B * NW + kk, par = k & 1;
+      const int r = __builtin_amdgcn_readfirstlane(sh.rsel[par]);
+      const double piv = sh.piv[par];
+      const bool ok = (piv != 0.0) && isfinite(piv);
+      const double ip = ok ? 1.0 / piv : 0.0;
+      const int ir = r >> 6, rl = r & 63;
+      if (lane == rl) umask |= 1u << ir;
+      double f[RA];
+#pragma unroll
+      for (int i = 0; i < RA; ++i) f[i] = sh.fbuf[par][lane + 64 * i] * ip;
+      double s[CB];
+      gj2_pivot_row<RA, CB>(a, ir, rl, s);
+      // slots B and B + 1 first: column k + 1 is in one of them
+#pragma unroll
+      for (int i = 0; i < RA; ++i) a[i][B] = fma(-f[i], s[B], a[i][B]);
+      if constexpr (B + 1 < CB) {
+#pragma unroll
+        for (int i = 0; i < RA; ++i) a[i][B + 1] = fma(-f[i], s[B + 1], a[i][B + 1]);
+      }
+      if (wid == kk) {
+#pragma unroll
+        for (int i = 0; i < RA; ++i) a[i][B] = -f[i];
+      }
+      if (kk + 1 < kend) {
+        if (wid == kk + 1) gj2_publish<NW, RA, CB>(a, umask, B, k + 1, lane, sh);
+      } else if (B + 1 < CB && k + 1 < n) {
+        if (wid == 0) gj2_publish<NW, RA, CB>(a, umask, B + 1 < CB ? B + 1 : B, k + 1, lane, sh);
+      }
+#pragma unroll
+      for (int i = 0; i < RA; ++i)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+          if (c != B && c != B + 1) a[i][c] = fma(-f[i], s[c], a[i][c]);
+      __syncthreads();
+    }
+    gj2_slots<NW, RA, CB, B + 1>(a, n, lane, wid, umask, sh);
+  }
+}
+
+template <int NW, int RA, int CB>
+__device__ __forceinline__ void gj2_core(double (&a)[RA][CB], const int n, const int lane,
+                                         const int wid, GJ2Shared<NW, RA> &sh) {
+  unsigned umask = 0u;                    // used (or padding) rows among my RA rows
+#pragma unroll
+  for (int i = 0; i < RA; ++i)
+    if (lane + 64 * i >= n) umask |= 1u << i;
+  if (threadIdx.x == 0) sh.info = 0;
+  __syncthreads();
+  if (wid == 0) gj2_publish<NW, RA, CB>(a, umask, 0, 0, lane, sh);
+  __syncthreads();
+  gj2_slots<NW, RA, CB, 0>(a, n, lane, wid, umask, sh);
+}
+
+// Leaf kernel on the column-owner core (same outputs as gj_leaf_kernel).
+template <int P, int NW, int RA, int CB>
+__global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
+    const LeafDesc *__restrict__ descs, int nleaf, Bases bs,
+    const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
+    const int32_t *__restrict__ ice, int me, int32_t *__restrict__ info) {
+  constexpr int PI = P - 2, MI = PI * PI;
+  static_assert(64 * RA >= MI && NW * CB >= MI, "block too small");
+  __shared__ GJ2Shared<NW, RA> sh;
+  __shared__ double cf[6][P * P];
+  __shared__ double Dh[P * P], Dh2[P * P];
+  const int leaf = blockIdx.x;
+  if (leaf >= nleaf) return;
+  const LeafDesc &d = descs[leaf];
+  const double *coef = (const double *)bs.d[BUF_IN0] + d.coef;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int i = tid; i < 6 * P * P; i += NW * 64) cf[i / (P * P)][i % (P * P)] = coef[i];
+  for (int i = tid; i < P * P; i += NW * 64) { Dh[i] = Dh_g[i]; Dh2[i] = Dh2_g[i]; }
+  __syncthreads();
+  const double sx = d.sx, sy = d.sy;
+  auto entry = [&](int ga, int gb) -> double {
+    const int iy = ga / P, ix = ga - iy * P, jy = gb / P, jx = gb - jy * P;
+    double v = -2.0 * cf[1][ga] * sx * sy * Dh[iy * P + jy] * Dh[ix * P + jx];
+    if (iy == jy) v += -cf[0][ga] * sx * sx * Dh2[ix * P + jx] + cf[3][ga] * sx * Dh[ix * P + jx];
+    if (ix == jx) v += -cf[2][ga] * sy * sy * Dh2[iy * P + jy] + cf[4][ga] * sy * Dh[iy * P + jy];
+    if (ga == gb) v += cf[5][ga];
+    return v;
+  };
+  auto grid_of = [](int a) { const int y = a / PI; return (y + 1) * P + (a - y * PI) + 1; };
+  double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
+  for (int idx = tid; idx < MI * me; idx += NW * 64) {
+    const int a = idx % MI, e = idx / MI;
+    Aie[idx] = entry(grid_of(a), ice[e]);
+  }
+  double a[RA][CB];
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = lane + 64 * i;
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = wid + NW * b;
+      a[i][b] = (row < MI && col < MI) ? entry(grid_of(row), grid_of(col)) : 0.0;
+    }
+  }
+  gj2_core<NW, RA, CB>(a, MI, lane, wid, sh);
+  double *F = (double *)bs.d[BUF_WS] + d.F;
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = lane + 64 * i;
+    if (row >= MI) continue;
+    const int kr = sh.stepof[row];
+    const double sg = sh.sig[kr];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = wid + NW * b;
+      if (col < MI)
+        F[kr + int64_t(sh.pivrow[col]) * MI] = sg * (a[i][b] + (col == kr ? 1.0 : 0.0));
+    }
+  }
+  if (tid == 0) info[d.info] = sh.info;
+}
+
 template <int TR, int TC, int RA, int CB>
 __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_merge_kernel(
     const MergeInvDesc *__restrict__ descs, int nd, Bases bs,
@@ -1044,8 +1250,8 @@ hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &
   if (nleaf <= 0) return hipSuccess;
   switch (p) {
     case 16:
-      hipLaunchKernelGGL((gj_leaf_kernel<16, 28, 36, 7, 6>), dim3(nleaf), dim3(gj_threads<28, 36>()), 0,
-                         st, descs, nleaf, bs, Dh, Dh2, ice, me, info);
+      hipLaunchKernelGGL((gj2_leaf_kernel<16, 8, 4, 25>), dim3(nleaf), dim3(512), 0, st, descs,
+                         nleaf, bs, Dh, Dh2, ice, me, info);
       break;
     case 12:
       hipLaunchKernelGGL((gj_leaf_kernel<12, 20, 20, 5, 5>), dim3(nleaf), dim3(gj_threads<20, 20>()), 0, st,
@@ -1133,8 +1339,12 @@ hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
                        kb, bs, g, info);
   else
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gj_wgather_kernel<16>), dim3(unsigned((maxm + 255) / 256), nd), dim3(256),
-                     0, st, descs, nd, kb, bs, g);
+  if (panel_nb(maxm) == 32)
+    hipLaunchKernelGGL((gj_wgather_kernel<32>), dim3(unsigned((maxm + 255) / 256), nd),
+                       dim3(256), 0, st, descs, nd, kb, bs, g);
+  else
+    hipLaunchKernelGGL((gj_wgather_kernel<16>), dim3(unsigned((maxm + 255) / 256), nd),
+                       dim3(256), 0, st, descs, nd, kb, bs, g);
   return hipGetLastError();
 }
 

@@ -180,3 +180,27 @@ def test_full_size_workload2_against_stored_oracle():
     assert relerr(u[ref["leaves"]], ref["u"]) <= TOL
     um = s.solve(to_dev(f[None]), to_dev(g[None]), precision=H.HPS_PREC_MIXED)[0].cpu().numpy()
     assert relerr(um[ref["leaves"]], ref["u"]) <= 1e-10
+
+
+def test_refactor_graph_replays_match_fresh_builds():
+    """Refactorization replays the build program as a captured HIP graph.
+    Alternate two coefficient sets over several replays, with eager solves
+    and synchronizations in between: every replay must give bit for bit the
+    operators of a fresh (eager) build with the same coefficients."""
+    import torch
+    H = _lib()
+    p, q = 12, 11
+    t = H.Tree(0, 1, 0, 1, 8, 8)
+    sol = W.FourierSolution(6)
+    c1, f, g, _ = lib_inputs(t, p, q, W.varcoeff, sol)
+    c2, _, _, _ = lib_inputs(t, p, q, W.heat_coeffs, sol)
+    fd, gd = to_dev(np.stack([f, 2 * f])), to_dev(np.stack([g, -g]))
+    refs = {}
+    for name, c in (("c1", c1), ("c2", c2)):
+        refs[name] = H.Solver(t, to_dev(c), p, q).solve(fd, gd).cpu().numpy()
+    s = H.Solver(t, to_dev(c1), p, q)
+    for i, name in enumerate(["c2", "c1", "c2", "c2", "c1"]):
+        s.refactor(to_dev(c2 if name == "c2" else c1))
+        u = s.solve(fd, gd).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(u, refs[name]), (i, name)
