@@ -24,6 +24,7 @@
 namespace hps {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 
 // Tiles handed out so that the blocks one XCD receives (block b runs on XCD
@@ -1031,27 +1032,46 @@ __device__ __forceinline__ void stage_regs(double (&breg)[KC * NR / 256], int mo
     if (!ok[j]) breg[j] = 0.0;
 }
 
-// FP64 apply on the matrix cores for 16 or more right-hand sides: the same
-// tiles (64 operator rows x one k-slice) as apply_kernel, with the 64 rows
-// split over the four wavefronts (16 each) and 16 x 16 x 4 MFMA steps over
-// k, so no cross-wavefront reduction is needed.  NT16 = right-hand-side
-// tiles of 16 per workgroup.  f64 MFMA operand layouts: lane l holds
-// A(l % 16, l / 16) and B(l / 16, l % 16); the result register v of lane l is
-// C((l >> 4) + 4 v, l & 15).
+// Matrix-core apply for 16 or more right-hand sides, FP64 or FP32 operators:
+// the same tiles (64 operator rows x one k-slice) as apply_kernel, with the
+// 64 rows split over the four wavefronts (16 each) and 16 x 16 x 4 MFMA
+// steps over k, so no cross-wavefront reduction is needed.  NT16 =
+// right-hand-side tiles of 16 per workgroup.  Operand layouts (both
+// precisions): lane l holds A(l % 16, l / 16) and B(l / 16, l % 16); result
+// register v of lane l is C((l >> 4) + 4 v, l & 15) for f64 and
+// C(4 (l >> 4) + v, l & 15) for f32.  FP32 operators accumulate in FP32 and
+// the result is widened to FP64 when stored.
 //
 // Software pipeline over k chunks of KC: the operator entries and the right
 // operand of chunk c + 1 are loaded into registers while chunk c runs on the
 // matrix cores; the right operand goes through a double-buffered LDS tile, so
 // one barrier per chunk suffices.  The right operand is read along its
 // contiguous direction (k for RHS-major arrays, right-hand sides otherwise).
-template <int NT16, bool TRANS>
+template <typename T> struct MfmaT;
+template <> struct MfmaT<double> {
+  typedef dbl4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct MfmaT<float> {
+  typedef flt4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename TA, int NT16, bool TRANS>
 __global__ __launch_bounds__(256) void apply_mfma_kernel(
     const ApplyDesc *__restrict__ descs, const int32_t *__restrict__ tmap,
     int64_t ntiles, Bases bs, int nrhs) {
+  typedef MfmaT<TA> M;
   constexpr int NR = 16 * NT16;
   constexpr int KC = 64;
   constexpr int NB = KC * NR / 256;          // right-operand entries per thread
-  __shared__ double Bsh[2][KC][NR + 1];
+  __shared__ TA Bsh[2][KC][NR + 1];
   __shared__ int ixs[3][512];               // gather indices of the tile's k range
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntiles) return;
@@ -1063,15 +1083,18 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
   const int k0 = slice * kper, k1 = min(K, k0 + kper);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int r0 = blockIdx.y * NR;
-  const double *A = (const double *)bs.d[d.abuf] + d.aoff;
+  const TA *A = (const TA *)bs.d[d.abuf] + d.aoff;
   const int lda = d.lda;
   const int arow = rbi * 64 + wid * 16 + (lane & 15);   // operand row of this lane
   const bool arow_ok = arow < d.M;
   const int kl = lane >> 4;
-  dbl4 acc[NT16];
+  typename M::acc_t acc[NT16];
 #pragma unroll
-  for (int u = 0; u < NT16; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-  double abuf[KC / 4], breg[NB];
+  for (int u = 0; u < NT16; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = TA(0);
+  TA abuf[KC / 4];
+  double breg[NB];
   const int mode = d.mode, K1 = d.K1;
   const VSrc s1 = vsrc(bs, d.B1, nrhs), s2 = vsrc(bs, d.B2, nrhs), s3 = vsrc(bs, d.B3, nrhs);
   for (int k = k0 + tid; k < k1; k += 256) {
@@ -1093,7 +1116,7 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
       abuf[j] = (arow_ok && kk < kn_)                                                       \
                     ? (TRANS ? A[int64_t(arow) * lda + (KCV) + kk]                          \
                              : A[arow + int64_t((KCV) + kk) * lda])                         \
-                    : 0.0;                                                                  \
+                    : TA(0);                                                                \
     }                                                                                       \
     const int kmid = (KCV) + min(kn_ - 1, KC / 2);                                          \
     KF = ((mode == 0 && kmid >= K1) ? s2.kmul : s1.kmul) == 1;                              \
@@ -1107,9 +1130,9 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
     for (int j = 0; j < NB; ++j) {
       const int kk = kfast ? tid % KC : tid / NR + (256 / NR) * j;
       const int r = kfast ? tid / KC + (256 / KC) * j : tid % NR;
-      Bsh[buf][kk][r] = breg[j];
+      Bsh[buf][kk][r] = TA(breg[j]);
     }
-    double acur[KC / 4];
+    TA acur[KC / 4];
 #pragma unroll
     for (int j = 0; j < KC / 4; ++j) acur[j] = abuf[j];
     __syncthreads();
@@ -1119,8 +1142,7 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
       const int kk = 4 * j + kl;
 #pragma unroll
       for (int u = 0; u < NT16; ++u)
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[j], Bsh[buf][kk][16 * u + (lane & 15)],
-                                                      acc[u], 0, 0, 0);
+        acc[u] = M::mma(acur[j], Bsh[buf][kk][16 * u + (lane & 15)], acc[u]);
     }
     buf ^= 1;
   }
@@ -1132,10 +1154,10 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
     for (int u = 0; u < NT16; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = rbi * 64 + wid * 16 + (lane >> 4) + 4 * v;
+        const int row = rbi * 64 + wid * 16 + M::row(lane, v);
         const int rg = r0 + 16 * u + (lane & 15);
         if (row >= d.M || rg >= nrhs) continue;
-        double val = d.alpha * acc[u][v];
+        double val = d.alpha * double(acc[u][v]);
         if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
         *vaddr(bs, d.C, row, rg, nrhs) = val;
       }
@@ -1148,7 +1170,7 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
   for (int u = 0; u < NT16; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      Bsh[buf][wid * 16 + (lane >> 4) + 4 * v][16 * u + (lane & 15)] = acc[u][v];
+      Bsh[buf][wid * 16 + M::row(lane, v)][16 * u + (lane & 15)] = acc[u][v];
   __syncthreads();
   const int row = rbi * 64 + lane;
   if (row >= d.M) return;
@@ -1156,7 +1178,7 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
   for (int j = 0; j < NR / 4; ++j) {
     const int r = wid + 4 * j, rg = r0 + r;
     if (rg >= nrhs) continue;
-    const double sv = Bsh[buf][lane][r];
+    const double sv = double(Bsh[buf][lane][r]);
     if (d.ksl == 1) {
       double val = d.alpha * sv;
       if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
@@ -1386,17 +1408,25 @@ static void launch_apply_t(const ApplyDesc *descs, const int32_t *tmap,
 hipError_t launch_apply(int prec, const ApplyDesc *descs, const int32_t *tmap,
                         int64_t ntiles, const Bases &bs, int nrhs, hipStream_t st, bool trans) {
   if (ntiles <= 0) return hipSuccess;
-  if (prec == 0 && nrhs >= 16) {
+  if (nrhs >= 16) {
     const int64_t nblk = (ntiles + 7) / 8 * 8;
     const bool two = nrhs > 16;
     const unsigned gy = unsigned((nrhs + (two ? 31 : 15)) / (two ? 32 : 16));
-#define HPS_APPLY_MFMA(NT, TR)                                                             \
-  hipLaunchKernelGGL((apply_mfma_kernel<NT, TR>), dim3(unsigned(nblk), gy), dim3(256), 0, st, \
-                     descs, tmap, ntiles, bs, nrhs)
-    if (two) {
-      if (trans) HPS_APPLY_MFMA(2, true); else HPS_APPLY_MFMA(2, false);
+#define HPS_APPLY_MFMA(TA, NT, TR)                                                           \
+  hipLaunchKernelGGL((apply_mfma_kernel<TA, NT, TR>), dim3(unsigned(nblk), gy), dim3(256), 0, \
+                     st, descs, tmap, ntiles, bs, nrhs)
+    if (prec == 0) {
+      if (two) {
+        if (trans) HPS_APPLY_MFMA(double, 2, true); else HPS_APPLY_MFMA(double, 2, false);
+      } else {
+        if (trans) HPS_APPLY_MFMA(double, 1, true); else HPS_APPLY_MFMA(double, 1, false);
+      }
     } else {
-      if (trans) HPS_APPLY_MFMA(1, true); else HPS_APPLY_MFMA(1, false);
+      if (two) {
+        if (trans) HPS_APPLY_MFMA(float, 2, true); else HPS_APPLY_MFMA(float, 2, false);
+      } else {
+        if (trans) HPS_APPLY_MFMA(float, 1, true); else HPS_APPLY_MFMA(float, 1, false);
+      }
     }
 #undef HPS_APPLY_MFMA
     return hipGetLastError();

@@ -3,6 +3,7 @@
 // updates and reductions, and the coefficient gradient of the adjoint.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -10,66 +11,73 @@
 
 namespace hps {
 
-// One workgroup per (leaf, right-hand side).  Residual of the collocated PDE
-// at interior nodes, r = g - A u (Sec. 3.2, same A as the build), and the
-// leaf's boundary fluxes D_ge,c u (Sec. 3.4) in side order S, E, N, W.
+// One workgroup per leaf, looping over the right-hand sides (the leaf's
+// coefficients and reference matrices are read once).  Residual of the
+// collocated PDE at interior nodes, r = g - A u (Sec. 3.2, same A as the
+// build), and the leaf's boundary fluxes D_ge,c u (Sec. 3.4) in side order
+// S, E, N, W.
 template <int P>
 __global__ __launch_bounds__(256) void residual_kernel(
     const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
     const double *__restrict__ uc, const double *__restrict__ g, double *__restrict__ r1,
     double *__restrict__ flux, const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
-    const double *__restrict__ Lloc_g, int q) {
+    const double *__restrict__ Lloc_g, int q, int nrhs) {
   constexpr int PP = P * P, PI = P - 2, MI = PI * PI;
   __shared__ double u[PP], dx[PP], dy[PP], Dh[PP], Dh2[PP], cf[6][PP], Lloc[P * P];
-  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int leaf = blockIdx.x, tid = threadIdx.x;
   const int64_t nl = nleaf;
   const LeafDesc &d = leafd[leaf];
   const double sx = d.sx, sy = d.sy;
   for (int i = tid; i < PP; i += 256) {
-    u[i] = uc[(int64_t(r) * nl + leaf) * PP + i];
     Dh[i] = Dh_g[i];
     Dh2[i] = Dh2_g[i];
   }
   for (int i = tid; i < q * P; i += 256) Lloc[i] = Lloc_g[i];
   for (int i = tid; i < 6 * PP; i += 256) cf[i / PP][i % PP] = coef[int64_t(leaf) * 6 * PP + i];
-  __syncthreads();
-  // reference-coordinate first derivatives on the whole grid
-  for (int t = tid; t < PP; t += 256) {
-    const int iy = t / P, ix = t - iy * P;
-    double sxv = 0.0, syv = 0.0;
-    for (int j = 0; j < P; ++j) {
-      sxv += Dh[ix * P + j] * u[iy * P + j];
-      syv += Dh[iy * P + j] * u[j * P + ix];
+  for (int r = 0; r < nrhs; ++r) {
+    for (int i = tid; i < PP; i += 256) u[i] = uc[(int64_t(r) * nl + leaf) * PP + i];
+    __syncthreads();
+    // reference-coordinate first derivatives on the whole grid
+    for (int t = tid; t < PP; t += 256) {
+      const int iy = t / P, ix = t - iy * P;
+      double sxv = 0.0, syv = 0.0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        sxv += Dh[ix * P + j] * u[iy * P + j];
+        syv += Dh[iy * P + j] * u[j * P + ix];
+      }
+      dx[t] = sxv;
+      dy[t] = syv;
     }
-    dx[t] = sxv;
-    dy[t] = syv;
-  }
-  __syncthreads();
-  for (int a = tid; a < MI; a += 256) {
-    const int y = a / PI, iy = y + 1, ix = a - y * PI + 1, t = iy * P + ix;
-    double uxx = 0.0, uyy = 0.0, uxy = 0.0;
-    for (int j = 0; j < P; ++j) {
-      uxx += Dh2[ix * P + j] * u[iy * P + j];
-      uyy += Dh2[iy * P + j] * u[j * P + ix];
-      uxy += Dh[iy * P + j] * dx[j * P + ix];
+    __syncthreads();
+    for (int a = tid; a < MI; a += 256) {
+      const int y = a / PI, iy = y + 1, ix = a - y * PI + 1, t = iy * P + ix;
+      double uxx = 0.0, uyy = 0.0, uxy = 0.0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        uxx += Dh2[ix * P + j] * u[iy * P + j];
+        uyy += Dh2[iy * P + j] * u[j * P + ix];
+        uxy += Dh[iy * P + j] * dx[j * P + ix];
+      }
+      const double Au = -cf[0][t] * sx * sx * uxx - 2.0 * cf[1][t] * sx * sy * uxy -
+                        cf[2][t] * sy * sy * uyy + cf[3][t] * sx * dx[t] + cf[4][t] * sy * dy[t] +
+                        cf[5][t] * u[t];
+      const int64_t o = (int64_t(r) * nl + leaf) * MI + a;
+      r1[o] = g[o] - Au;
     }
-    const double Au = -cf[0][t] * sx * sx * uxx - 2.0 * cf[1][t] * sx * sy * uxy -
-                      cf[2][t] * sy * sy * uyy + cf[3][t] * sx * dx[t] + cf[4][t] * sy * dy[t] +
-                      cf[5][t] * u[t];
-    const int64_t o = (int64_t(r) * nl + leaf) * MI + a;
-    r1[o] = g[o] - Au;
-  }
-  for (int k = tid; k < 4 * q; k += 256) {
-    const int side = k / q, kk = k - side * q;
-    double v = 0.0;
-    for (int j = 0; j < P; ++j) {
-      const double l = Lloc[kk * P + j];
-      if (side == 0) v += l * sy * dy[0 * P + j];
-      else if (side == 1) v += l * sx * dx[j * P + (P - 1)];
-      else if (side == 2) v += l * sy * dy[(P - 1) * P + j];
-      else v += l * sx * dx[j * P + 0];
+    for (int k = tid; k < 4 * q; k += 256) {
+      const int side = k / q, kk = k - side * q;
+      double v = 0.0;
+      for (int j = 0; j < P; ++j) {
+        const double l = Lloc[kk * P + j];
+        if (side == 0) v += l * sy * dy[0 * P + j];
+        else if (side == 1) v += l * sx * dx[j * P + (P - 1)];
+        else if (side == 2) v += l * sy * dy[(P - 1) * P + j];
+        else v += l * sx * dx[j * P + 0];
+      }
+      flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
     }
-    flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
+    __syncthreads();   // u, dx, dy are rewritten for the next right-hand side
   }
 }
 
@@ -166,27 +174,27 @@ hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double
                            const double *uc, const double *g, double *r1, double *flux,
                            const double *Dh, const double *Dh2, const double *Lloc, int q,
                            int nrhs, hipStream_t st) {
-  dim3 grid(nleaf, nrhs);
+  dim3 grid(nleaf);
   switch (p) {
     case 16:
       hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q);
+                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 12:
       hipLaunchKernelGGL(residual_kernel<12>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q);
+                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 10:
       hipLaunchKernelGGL(residual_kernel<10>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q);
+                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 8:
       hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q);
+                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 6:
       hipLaunchKernelGGL(residual_kernel<6>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q);
+                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     default:
       return hipErrorInvalidValue;
@@ -214,7 +222,10 @@ hipError_t launch_maxabs2(const double *a, const double *b, int64_t n, double *o
                           hipStream_t st) {
   unsigned long long *o = reinterpret_cast<unsigned long long *>(out);
   hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(64), 0, st, o);
-  hipLaunchKernelGGL(maxabs2_kernel, dim3(grid1(n / 4 + 1)), dim3(256), 0, st, a, b, n, o);
+  // a few workgroups per CU: each merges its maximum with one atomic
+  const int64_t nb = std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(maxabs2_kernel, dim3(unsigned(nb < 1 ? 1 : nb)), dim3(256), 0, st, a, b, n,
+                     o);
   return hipGetLastError();
 }
 
