@@ -64,7 +64,7 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
   if (rc) return rc;
   SolveExt &E = *H->ext;
   const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 6;
-  const double tol = opts && opts->ir_tol > 0.0 ? opts->ir_tol : 1e-13;
+  const double tol = opts && opts->ir_tol > 0.0 ? opts->ir_tol : 1e-11;
   const int64_t N = H->pl.n_gauss;
   const int64_t ucn = int64_t(H->nleaf) * H->p * H->p;
   // first FP32 pass on the original data

@@ -193,7 +193,7 @@ class Solver:
             raise ValueError("coeffs has the wrong shape")
         _check(lib().hps_refactor(self._h, _dev_ptr(coeffs, "coeffs"), _stream(stream)))
 
-    def solve(self, f, g, precision=HPS_PREC_FP64, ir_tol=1e-13, max_iter=0,
+    def solve(self, f, g, precision=HPS_PREC_FP64, ir_tol=1e-11, max_iter=0,
               u_gauss=False, stream=None, stats=None):
         """f: [nrhs, n_bdry], g: [nrhs, n_leaves, (p-2)^2] -> u [nrhs, n_leaves, p^2]."""
         torch = self._torch
