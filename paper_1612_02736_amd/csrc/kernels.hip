@@ -440,6 +440,16 @@ struct GJ2Shared {
   int info;
 };
 
+// 1 / x by the hardware reciprocal refined with two Newton steps
+// (r <- r + r (1 - x r)), within an ulp or two of the division; x must be
+// finite and nonzero.
+__device__ __forceinline__ double recip_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = __builtin_amdgcn_readlane(int(unsigned(b)), l);
@@ -483,19 +493,23 @@ __device__ __forceinline__ void gj2_publish(const double (&a)[RA][CB], unsigned 
     sh.pivrow[k] = r;
     sh.stepof[r] = k;
     const bool ok = (pv != 0.0) && isfinite(pv);
-    sh.sig[k] = ok ? 1.0 / pv : 0.0;
+    sh.sig[k] = ok ? recip_f64(pv) : 0.0;
     if (!ok && sh.info == 0) sh.info = isfinite(pv) ? (k + 1) : -(k + 1);
   }
 }
 
-template <int RA, int CB>
+// Pivot-row entries of every slot except SKIP and SKIP + 1 (already used).
+template <int RA, int CB, int SKIP>
 __device__ __forceinline__ void gj2_pivot_row(const double (&a)[RA][CB], int ir, int rl,
                                               double (&s)[CB]) {
+#pragma unroll
+  for (int b = 0; b < CB; ++b) s[b] = 0.0;
 #pragma unroll
   for (int i = 0; i < RA; ++i)
     if (i == ir) {
 #pragma unroll
-      for (int b = 0; b < CB; ++b) s[b] = readlane_f64(a[i][b], rl);
+      for (int b = 0; b < CB; ++b)
+        if (b != SKIP && b != SKIP + 1) s[b] = readlane_f64(a[i][b], rl);
     }
 }
 
@@ -511,20 +525,27 @@ __device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, cons
       const int r = __builtin_amdgcn_readfirstlane(sh.rsel[par]);
       const double piv = sh.piv[par];
       const bool ok = (piv != 0.0) && isfinite(piv);
-      const double ip = ok ? 1.0 / piv : 0.0;
+      const double ip = ok ? recip_f64(piv) : 0.0;
       const int ir = r >> 6, rl = r & 63;
       if (lane == rl) umask |= 1u << ir;
       double f[RA];
 #pragma unroll
       for (int i = 0; i < RA; ++i) f[i] = sh.fbuf[par][lane + 64 * i] * ip;
-      double s[CB];
-      gj2_pivot_row<RA, CB>(a, ir, rl, s);
-      // slots B and B + 1 first: column k + 1 is in one of them
+      // slots B and B + 1 first (column k + 1 is in one of them), with only
+      // their pivot-row entries read, so the owner of column k + 1 reaches
+      // its publication early; then the other pivot-row entries and slots
+      double sB = 0.0, sB1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < RA; ++i) a[i][B] = fma(-f[i], s[B], a[i][B]);
+      for (int i = 0; i < RA; ++i)
+        if (i == ir) {
+          sB = readlane_f64(a[i][B], rl);
+          if constexpr (B + 1 < CB) sB1 = readlane_f64(a[i][B + 1], rl);
+        }
+#pragma unroll
+      for (int i = 0; i < RA; ++i) a[i][B] = fma(-f[i], sB, a[i][B]);
       if constexpr (B + 1 < CB) {
 #pragma unroll
-        for (int i = 0; i < RA; ++i) a[i][B + 1] = fma(-f[i], s[B + 1], a[i][B + 1]);
+        for (int i = 0; i < RA; ++i) a[i][B + 1] = fma(-f[i], sB1, a[i][B + 1]);
       }
       if (wid == kk) {
 #pragma unroll
@@ -535,6 +556,8 @@ __device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, cons
       } else if (B + 1 < CB && k + 1 < n) {
         if (wid == 0) gj2_publish<NW, RA, CB>(a, umask, B + 1 < CB ? B + 1 : B, k + 1, lane, sh);
       }
+      double s[CB];
+      gj2_pivot_row<RA, CB, B>(a, ir, rl, s);
 #pragma unroll
       for (int i = 0; i < RA; ++i)
 #pragma unroll
