@@ -287,7 +287,7 @@ void gemm_step(GemmList &gl, GemmList &tmp, std::vector<Step> &prog) {
 // Launch steps that invert the interface blocks of one level: the
 // register-resident kernel per size class, the blocked path above it.
 void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeInvDesc> &minv,
-                        GemmList &gl, std::vector<Step> &prog) {
+                        std::vector<Step> &prog) {
   std::vector<MergeInvDesc> cls_d[4], big;
   int bigmax = 0;
   for (const MergeInvDesc &d : lev) {
@@ -311,32 +311,12 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
   Step z{S_ZDIFF};
   z.d0 = d0; z.nd = (int64_t)big.size(); z.maxm = bigmax;
   prog.push_back(z);
-  for (int kb = 0; kb < bigmax; kb += NBp) {
+  // launch kb applies panel kb's update to the other columns and sweeps
+  // panel kb + NB (kb = -NB: only the sweep of panel 0)
+  for (int kb = -NBp; kb < bigmax; kb += NBp) {
     Step s{S_PANEL};
     s.d0 = d0; s.nd = (int64_t)big.size(); s.kb = kb; s.maxm = bigmax;
     prog.push_back(s);
-    // columns outside the panel: B <- B + P W (the panel kernel has zeroed
-    // the pivot rows of B and copied their old values to W)
-    GemmList up;
-    for (const MergeInvDesc &d : big) {
-      const int m = d.m;
-      if (kb >= m) continue;
-      const int nbv = std::min(NBp, m - kb), ke = kb + nbv;
-      const int cols[2][2] = {{0, kb}, {ke, m}};
-      for (int ci = 0; ci < 2; ++ci) {
-        const int c0 = cols[ci][0], c1 = cols[ci][1];
-        if (c1 <= c0) continue;
-        GemmDesc g{};
-        g.M = m; g.N = c1 - c0; g.K = nbv;
-        g.A = ref(BUF_WS, d.X + int64_t(kb) * m, m);
-        g.B = ref(BUF_SCR, d.W + int64_t(c0) * NBp, NBp);
-        g.C = ref(BUF_WS, d.X + int64_t(c0) * m, m);
-        g.D = ref(BUF_WS, d.X + int64_t(c0) * m, m);
-        g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 1.0;
-        up.add(g);
-      }
-    }
-    gemm_step(gl, up, prog);
   }
   Step cp{S_COLPERM};
   cp.d0 = d0; cp.nd = (int64_t)big.size(); cp.maxm = bigmax;
@@ -614,7 +594,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       d.ipiv = Lo.ipiv[b];
       levd.push_back(d);
     }
-    emit_inverse_steps(levd, minv, gl, prog);
+    emit_inverse_steps(levd, minv, prog);
     // S = X [-T31a | T32b]
     GemmList sg, tg, c1, c2;
     for (int b : lev) {
@@ -1118,8 +1098,12 @@ static void annotate_work(std::vector<Step> &prog, const GemmList &gl,
         case S_GJ_LEAF: w += 2.0 * double(mi) * mi * mi; break;
         case S_GJ_MERGE: w += 2.0 * double(mv[i].m) * mv[i].m * mv[i].m; break;
         case S_PANEL: {
-          const double nb = std::min(panel_nb(s.maxm), mv[i].m - s.kb);
-          if (nb > 0) w += 2.0 * mv[i].m * nb * nb;
+          // update by panel kb of the other columns, sweep of panel kb + NB
+          const int NBp = panel_nb(s.maxm), m = mv[i].m;
+          const double nu = s.kb >= 0 ? std::min(NBp, m - s.kb) : 0;
+          const double ns = std::min(NBp, m - (s.kb + NBp));
+          if (nu > 0) w += 2.0 * m * (m - nu) * nu;
+          if (ns > 0) w += 2.0 * m * ns * ns;
           break;
         }
         case S_APPLY:
@@ -1483,7 +1467,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   }
   GemmList gl;
   std::vector<Step> prog;
-  emit_inverse_steps(lev, minv, gl, prog);
+  emit_inverse_steps(lev, minv, prog);
   HIPCHK(H.d_minv.upload(minv));
   HIPCHK(H.d_gemm.upload(gl.d));
   HIPCHK(H.d_gemm_tmap.upload(gl.tmap));
