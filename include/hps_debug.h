@@ -46,7 +46,9 @@ int hps_debug_box_op(const hps_handle *h, int box, int which, double *out, int64
  * solves on this handle is bracketed by HIP events on the caller's stream.
  * hps_debug_profile_read waits for the device, returns (kind, ms, work)
  * triples of the steps recorded since the last read (kind = 16 * step type +
- * variant: types 0 GEMM, 1 leaf Gauss-Jordan, 2 interface Gauss-Jordan,
+ * variant, the variant being the size class of an interface Gauss-Jordan
+ * and 0 otherwise; types 0 GEMM,
+ * 1 leaf Gauss-Jordan, 2 interface Gauss-Jordan,
  * 3 interface difference, 4 panel, 5 column permutation, 6 solve apply) and
  * clears them.  work is the launch's algorithmic flop count (GEMM,
  * Gauss-Jordan, panel) or the number of operator elements it applies to each

@@ -33,17 +33,19 @@ struct GemmList {
   std::vector<GemmDesc> d;
   std::vector<int32_t> tmap;   // owning descriptor of each tile (index into d)
   int64_t tiles = 0;
-  void add(const GemmDesc &g0) {
+  void add(const GemmDesc &g0) {   // 64 x 64 tiles
     GemmDesc g = g0;
+    if (g.M <= 0 || g.N <= 0) return;
     g.tn = (g.N + 63) / 64;
     const int64_t tm = (g.M + 63) / 64;
-    if (g.M <= 0 || g.N <= 0) return;
     g.tile0 = tiles;
     tiles += tm * g.tn;
     tmap.insert(tmap.end(), size_t(tm * g.tn), int32_t(d.size()));
     d.push_back(g);
   }
 };
+
+
 
 Ref ref(int32_t buf, int64_t off, int32_t ld) { return Ref{buf, ld, off}; }
 Ref noref() { return Ref{-1, 0, 0}; }

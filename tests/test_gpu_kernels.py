@@ -24,8 +24,13 @@ def _H():
 
 
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (64, 64, 16), (196, 60, 196),
-                                   (100, 300, 37), (130, 70, 1)])
+                                   (100, 300, 37), (130, 70, 1),
+                                   (128, 128, 256), (300, 260, 301), (960, 128, 961),
+                                   (129, 1000, 3)])
 def test_gemm_matches_numpy(M, N, K):
+    """The grouped GEMM against numpy: partial MFMA tiles, wavefronts whose
+    part of a tile lies outside the matrix, and K tails that are not a
+    multiple of the chunk or of the MFMA depth."""
     import torch
     from paper_1612_02736_amd.hps import debug_gemm
     rng = np.random.default_rng(M * 1000 + N + K)
