@@ -453,7 +453,7 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Column-owner Gauss-Jordan (one barrier per step)
+// Column-owner Gauss-Jordan (flag-synchronised, no barrier per step)
 // ---------------------------------------------------------------------------
 // NW wavefronts; lane l owns rows l + 64 i (i < RA) and wavefront w owns
 // columns w + NW b (b < CB), so a whole column lives in one wavefront.  Step
@@ -464,17 +464,29 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
 // value in LDS; every wavefront reads its part of the pivot row from its own
 // registers (readlane of lane r mod 64) and applies the rank-1 update, the
 // owner of column k + 1 updating and publishing that column before its
-// others.  One barrier per step.  Pivot rows stay unscaled as in gj_core.
+// others.  There is no barrier per step: published steps live in a ring of D
+// LDS slots, a wavefront starts step k once the counter `ready` has reached
+// k, and the owner of column k + 1 reuses the slot of step k + 1 - D once
+// every wavefront's `done` counter shows it has read that step.  Each step
+// waits only on steps before it, so the waits always end; each is bounded
+// all the same.  Pivot rows stay unscaled as in gj_core.
 template <int NW, int RA>
 struct GJ2Shared {
-  double fbuf[2][64 * RA];   // published pivot column (pivot row entry 0)
-  double piv[2];
-  int rsel[2];
+  static constexpr int D = 4;   // published steps held at once (a ring)
+  double fbuf[D][64 * RA];   // published pivot column (pivot row entry 0)
+  double piv[D];
+  int rsel[D];
   double sig[64 * RA];       // 1 / pivot of step k
   int pivrow[64 * RA];
   int stepof[64 * RA];
   int info;
+  int ready;                 // last published step
+  int done[NW];              // last step each wavefront has read
+  int abort;                 // a wait ran out (never in a correct run)
 };
+
+// Error code left in info when a wait of the flag-synchronised sweep ran out.
+constexpr int kGjSyncTimeout = -0x7fffffff;
 
 // 1 / x by the hardware reciprocal refined with two Newton steps
 // (r <- r + r (1 - x r)), within an ulp or two of the division; x must be
@@ -516,7 +528,7 @@ __device__ __forceinline__ void gj2_publish(const double (&a)[RA][CB], unsigned 
   const unsigned wmax = wave_max_u32(key);
   const int r = __builtin_amdgcn_readfirstlane(key_row(wmax));
   const int ir = r >> 6, rl = r & 63;
-  const int par = k & 1;
+  const int par = k % GJ2Shared<NW, RA>::D;
   double pv = 0.0;
 #pragma unroll
   for (int i = 0; i < RA; ++i) {
@@ -531,6 +543,49 @@ __device__ __forceinline__ void gj2_publish(const double (&a)[RA][CB], unsigned 
     const bool ok = (pv != 0.0) && isfinite(pv);
     sh.sig[k] = ok ? recip_f64(pv) : 0.0;
     if (!ok && sh.info == 0) sh.info = isfinite(pv) ? (k + 1) : -(k + 1);
+    // the wavefront's LDS writes above are performed in order, so a reader
+    // that sees ready >= k also sees step k's column, row and pivot
+    __hip_atomic_store(&sh.ready, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Bounded waits of the flag-synchronised sweep: each spins (with s_sleep)
+// until its condition holds, and gives up after 2^20 polls, setting abort so
+// that every later wait returns at once and the kernel ends (the result is
+// then reported as failed through info).
+template <int NW, int RA>
+__device__ __forceinline__ void gj2_giveup(GJ2Shared<NW, RA> &sh) {
+  __hip_atomic_store(&sh.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int NW, int RA>
+__device__ __forceinline__ void gj2_wait_ready(GJ2Shared<NW, RA> &sh, int k) {
+  for (unsigned spins = 0;; ++spins) {
+    const int v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&sh.ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (v >= k) return;
+    if (__builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&sh.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)))
+      return;
+    if (spins >= (1u << 20)) { gj2_giveup(sh); return; }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// every wavefront has read step k (so its ring slot may be reused)
+template <int NW, int RA>
+__device__ __forceinline__ void gj2_wait_done(GJ2Shared<NW, RA> &sh, int k) {
+  for (unsigned spins = 0;; ++spins) {
+    int m = __hip_atomic_load(&sh.done[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      m = min(m, __hip_atomic_load(&sh.done[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (__builtin_amdgcn_readfirstlane(m) >= k) return;
+    if (__builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&sh.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)))
+      return;
+    if (spins >= (1u << 20)) { gj2_giveup(sh); return; }
+    __builtin_amdgcn_s_sleep(1);
   }
 }
 
@@ -555,9 +610,11 @@ template <int NW, int RA, int CB, int B>
 __device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, const int lane,
                                           const int wid, unsigned &umask, GJ2Shared<NW, RA> &sh) {
   if constexpr (B < CB) {
+    constexpr int D = GJ2Shared<NW, RA>::D;
     const int kend = min(NW, n - B * NW);
     for (int kk = 0; kk < kend; ++kk) {
-      const int k = B * NW + kk, par = k & 1;
+      const int k = B * NW + kk, par = k % D;
+      gj2_wait_ready(sh, k);
       const int r = __builtin_amdgcn_readfirstlane(sh.rsel[par]);
       const double piv = sh.piv[par];
       const bool ok = (piv != 0.0) && isfinite(piv);
@@ -567,6 +624,9 @@ __device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, cons
       double f[RA];
 #pragma unroll
       for (int i = 0; i < RA; ++i) f[i] = sh.fbuf[par][lane + 64 * i] * ip;
+      // step k read (the wavefront's LDS accesses are performed in order)
+      if (lane == 0)
+        __hip_atomic_store(&sh.done[wid], k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       // slots B and B + 1 first (column k + 1 is in one of them), with only
       // their pivot-row entries read, so the owner of column k + 1 reaches
       // its publication early; then the other pivot-row entries and slots
@@ -587,10 +647,18 @@ __device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, cons
 #pragma unroll
         for (int i = 0; i < RA; ++i) a[i][B] = -f[i];
       }
+      // the owner of column k + 1 publishes step k + 1 once every wavefront
+      // has read step k + 1 - D, whose ring slot it reuses
       if (kk + 1 < kend) {
-        if (wid == kk + 1) gj2_publish<NW, RA, CB>(a, umask, B, k + 1, lane, sh);
+        if (wid == kk + 1) {
+          gj2_wait_done(sh, k + 1 - D);
+          gj2_publish<NW, RA, CB>(a, umask, B, k + 1, lane, sh);
+        }
       } else if (B + 1 < CB && k + 1 < n) {
-        if (wid == 0) gj2_publish<NW, RA, CB>(a, umask, B + 1 < CB ? B + 1 : B, k + 1, lane, sh);
+        if (wid == 0) {
+          gj2_wait_done(sh, k + 1 - D);
+          gj2_publish<NW, RA, CB>(a, umask, B + 1 < CB ? B + 1 : B, k + 1, lane, sh);
+        }
       }
       double s[CB];
       gj2_pivot_row<RA, CB, B>(a, ir, rl, s);
@@ -599,7 +667,6 @@ __device__ __forceinline__ void gj2_slots(double (&a)[RA][CB], const int n, cons
 #pragma unroll
         for (int c = 0; c < CB; ++c)
           if (c != B && c != B + 1) a[i][c] = fma(-f[i], s[c], a[i][c]);
-      __syncthreads();
     }
     gj2_slots<NW, RA, CB, B + 1>(a, n, lane, wid, umask, sh);
   }
@@ -612,11 +679,18 @@ __device__ __forceinline__ void gj2_core(double (&a)[RA][CB], const int n, const
 #pragma unroll
   for (int i = 0; i < RA; ++i)
     if (lane + 64 * i >= n) umask |= 1u << i;
-  if (threadIdx.x == 0) sh.info = 0;
+  if (threadIdx.x == 0) {
+    sh.info = 0;
+    sh.ready = -1;
+    sh.abort = 0;
+  }
+  if (threadIdx.x < NW) sh.done[threadIdx.x] = -1;
   __syncthreads();
   if (wid == 0) gj2_publish<NW, RA, CB>(a, umask, 0, 0, lane, sh);
-  __syncthreads();
   gj2_slots<NW, RA, CB, 0>(a, n, lane, wid, umask, sh);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh.abort) sh.info = kGjSyncTimeout;
+  __syncthreads();
 }
 
 // Leaf kernel on the column-owner core (same outputs as gj_leaf_kernel).
