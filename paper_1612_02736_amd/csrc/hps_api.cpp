@@ -1286,6 +1286,8 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
     if (info[i] != 0) {
       const bool leaf = i < H->nleaf;
       const std::string what = leaf ? "leaf " + std::to_string(i) : "merge " + std::to_string(i - H->nleaf);
+      if (info[i] == kGjSyncTimeout)
+        return fail(HPS_EHIP, "synchronisation wait timed out in the Gauss-Jordan of " + what);
       if (info[i] > 0)
         return fail(HPS_ESINGULAR, "zero pivot at step " + std::to_string(info[i]) + " of " + what);
       return fail(HPS_ENONFINITE, "non-finite pivot at step " + std::to_string(-info[i]) + " of " + what);
@@ -1349,6 +1351,8 @@ int hps_refactor(hps_handle *H, const double *coeffs, void *stream) {
     if (info[i] != 0) {
       const std::string what = i < H->nleaf ? "leaf " + std::to_string(i)
                                             : "merge " + std::to_string(i - H->nleaf);
+      if (info[i] == kGjSyncTimeout)
+        return fail(HPS_EHIP, "synchronisation wait timed out in the Gauss-Jordan of " + what);
       if (info[i] > 0)
         return fail(HPS_ESINGULAR, "zero pivot at step " + std::to_string(info[i]) + " of " + what);
       return fail(HPS_ENONFINITE, "non-finite pivot at step " + std::to_string(-info[i]) + " of " + what);

@@ -481,12 +481,10 @@ struct GJ2Shared {
   int stepof[64 * RA];
   int info;
   int ready;                 // last published step
-  int done[NW];              // last step each wavefront has read
+  int done[NW];              // last step each wavefront has finished with
   int abort;                 // a wait ran out (never in a correct run)
 };
 
-// Error code left in info when a wait of the flag-synchronised sweep ran out.
-constexpr int kGjSyncTimeout = -0x7fffffff;
 
 // 1 / x by the hardware reciprocal refined with two Newton steps
 // (r <- r + r (1 - x r)), within an ulp or two of the division; x must be

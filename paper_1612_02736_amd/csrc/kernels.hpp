@@ -13,6 +13,9 @@ constexpr int kPanelNBMax = 32;   // widest panel of the blocked Gauss-Jordan
 int panel_nb(int maxm);           // panel width used for a level of size maxm
 
 // tmap[t] = index (into descs) of the descriptor that owns tile t
+// info code of a leaf Gauss-Jordan whose flag-synchronised sweep gave up
+// waiting (never in a correct run)
+constexpr int kGjSyncTimeout = -0x7fffffff;
 hipError_t launch_gemm(const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
                        const Bases &bs, hipStream_t st);
 int gj_leaf_supported(int p);
