@@ -1266,7 +1266,10 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
     int64_t ntiles, Bases bs, int nrhs) {
   typedef MfmaT<TA> M;
   constexpr int NR = 16 * NT16;
-  constexpr int KC = 64;
+  // k per chunk: 32 for FP64 operators (four wavefronts per SIMD fit in the
+  // register file, so more workgroups keep operator loads in flight), 64 for
+  // FP32
+  constexpr int KC = sizeof(TA) == 8 ? 32 : 64;
   constexpr int NB = KC * NR / 256;          // right-operand entries per thread
   __shared__ TA Bsh[2][KC][NR + 1];
   __shared__ int ixs[3][512];               // gather indices of the tile's k range
@@ -1284,6 +1287,8 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
   const int lda = d.lda;
   const int arow = rbi * 64 + wid * 16 + (lane & 15);   // operand row of this lane
   const bool arow_ok = arow < d.M;
+  // a wavefront whose 16 rows all lie past M only helps stage the right operand
+  const bool wave_on = rbi * 64 + __builtin_amdgcn_readfirstlane(wid) * 16 < d.M;
   const int kl = lane >> 4;
   typename M::acc_t acc[NT16];
 #pragma unroll
@@ -1334,12 +1339,14 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
     for (int j = 0; j < KC / 4; ++j) acur[j] = abuf[j];
     __syncthreads();
     if (kc + KC < k1) HPS_LOAD_CHUNK(kc + KC, kfast);
+    if (wave_on) {
 #pragma unroll
-    for (int j = 0; j < KC / 4; ++j) {
-      const int kk = 4 * j + kl;
+      for (int j = 0; j < KC / 4; ++j) {
+        const int kk = 4 * j + kl;
 #pragma unroll
-      for (int u = 0; u < NT16; ++u)
-        acc[u] = M::mma(acur[j], Bsh[buf][kk][16 * u + (lane & 15)], acc[u]);
+        for (int u = 0; u < NT16; ++u)
+          acc[u] = M::mma(acur[j], Bsh[buf][kk][16 * u + (lane & 15)], acc[u]);
+      }
     }
     buf ^= 1;
   }
@@ -1361,13 +1368,16 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
     return;
   }
   // RHS-major result or split-K partials: transpose through LDS so that
-  // lanes run along rows (buffer `buf` was last read two chunks ago)
+  // lanes run along rows, in the 2 KC >= 64 rows of both right-operand
+  // buffers (free after the barrier)
+  static_assert(2 * KC >= 64, "transpose needs 64 rows");
+  TA (*tr)[NR + 1] = reinterpret_cast<TA (*)[NR + 1]>(&Bsh[0][0][0]);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < NT16; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      Bsh[buf][wid * 16 + M::row(lane, v)][16 * u + (lane & 15)] = acc[u][v];
+      tr[wid * 16 + M::row(lane, v)][16 * u + (lane & 15)] = acc[u][v];
   __syncthreads();
   const int row = rbi * 64 + lane;
   if (row >= d.M) return;
@@ -1375,7 +1385,7 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(
   for (int j = 0; j < NR / 4; ++j) {
     const int r = wid + 4 * j, rg = r0 + r;
     if (rg >= nrhs) continue;
-    const double sv = double(Bsh[buf][lane][r]);
+    const double sv = double(tr[lane][r]);
     if (d.ksl == 1) {
       double val = d.alpha * sv;
       if (d.D.buf >= 0) val += d.beta * vload(bs, d.D, row, rg, nrhs);
