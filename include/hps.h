@@ -9,7 +9,7 @@
  * a p x p Chebyshev grid and q Gauss nodes per side (Babb, Gillman, Hao,
  * Martinsson, arXiv:1612.02736: problem statement eqs. basic/defA, leaf
  * discretisation Sec. 3, merge Sec. 4, Algorithms 1 and 2, local refinement
- * Sec. 5).
+ * Sec. 6).
  *
  * Conventions shared by every entry point
  *  - Return value: HPS_OK (0) or a negative HPS_E* code; a thread-local text
@@ -71,6 +71,13 @@ typedef struct {
   void *stream;          /* hipStream_t; 0 -> null stream */
   int keep_fp32;         /* 1: also keep FP32 copies of the solve operators
                             (needed for HPS_PREC_MIXED solves) */
+  int economic;          /* 1: storage-economic version (the remark on a
+                            storage efficient version, Sec. 5.4): the leaf
+                            solution operators F are not kept, and every
+                            solve redoes the leaf Gauss-Jordan eliminations
+                            in chunks of 1024 leaves to apply F g.  Removes
+                            the N q^2 storage term; FP64 forward solves only
+                            (no keep_fp32, no adjoint). */
 } hps_build_opts;
 
 enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
@@ -99,7 +106,7 @@ typedef struct {
 int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
                      int ny, int n_problems, hps_tree **out);
 
-/* Sec. 5.1: n_ref rounds of splitting into 2 x 2 every leaf of problem
+/* Sec. 6.1: n_ref rounds of splitting into 2 x 2 every leaf of problem
  * `problem` whose distance to (px, py) is <= t * (half its side); t = sqrt(2)
  * in the paper.  Must be called before hps_build; invalidates earlier
  * node queries. */
@@ -131,7 +138,7 @@ void hps_tree_free(hps_tree *tree);
 
 /* coeffs: device [n_leaves][6][p*p], nodal c11, c12, c22, c1, c2, c.
  * Builds F, S, H, T on every leaf (Sec. 3) and X, S, T on every merge
- * (Sec. 4), with P_up/P_down on refined interfaces (Sec. 5.3).  The handle
+ * (Sec. 4), with P_up/P_down on refined interfaces (Sec. 6.3).  The handle
  * owns the operators (device memory) and keeps a copy of the tree.
  * Errors: HPS_EINVAL (p < 4, q < 2, q >= p, NULL), HPS_ESINGULAR (message
  * names the first failing box), HPS_ENONFINITE, HPS_EHIP, HPS_ENOMEM.  On
@@ -149,20 +156,26 @@ int hps_refactor(hps_handle *h, const double *coeffs, void *stream);
 /* Device bytes the operators of a build take (FP64 only). */
 size_t hps_build_workspace_size(const hps_tree *tree, int p, int q);
 
+/* The same for a build with hps_build_opts.economic = economic. */
+size_t hps_build_workspace_size_econ(const hps_tree *tree, int p, int q, int economic);
+
 /* -- solve stage (Algorithm 2) -------------------------------------------- */
 
 /* f: device [nrhs][n_bdry] (canonical boundary order);
  * g: device [nrhs][n_leaves][(p-2)^2] (interior Chebyshev nodes);
  * u: device out [nrhs][n_leaves][p*p].
  * Upward pass h = H g, w = X(h3b - h3a), h = [h1a; h2b] + [T13a; T23b] w;
- * downward pass u_gi = S u_ge + w, u_c = S u_ge + F g (Algorithm 2). */
+ * downward pass u_gi = S u_ge + w, u_c = S u_ge + F g (Algorithm 2); on an
+ * economic build F g is recomputed through the leaf Gauss-Jordan
+ * eliminations, one chunk of leaves at a time (FP64 only). */
 int hps_solve(hps_handle *h, const double *f, const double *g, int nrhs,
               double *u, const hps_solve_opts *opts);
 
 /* Transpose of the linear map (f, g) -> u_c of hps_solve (not in the
  * paper): given ubar [nrhs][n_leaves][p*p] (device) returns
  * fbar [nrhs][n_bdry] and gbar [nrhs][n_leaves][(p-2)^2] (device) by the
- * transposed sweeps, reusing the stored operators. */
+ * transposed sweeps, reusing the stored operators (HPS_EINVAL on an economic
+ * build, which keeps no F). */
 int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs,
                       double *fbar, double *gbar, const hps_solve_opts *opts);
 

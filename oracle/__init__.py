@@ -14,7 +14,7 @@ solver based on multidomain spectral discretization" (arXiv:1612.02736):
                    local refinement towards a point (Sec. 2, 4, 5.1, 5.2).
 * ``leaf``      -- leaf operators F, S, H, T (Sec. 3, eqs. alpine1-alpine4).
 * ``hps``       -- Algorithm 1 (build) and Algorithm 2 (solve) with explicit
-                   per-box loops, plus the interface interpolation of Sec. 5.3
+                   per-box loops, plus the interface interpolation of Sec. 6.3
                    and 5.4 and the transposed (adjoint) sweeps.
 * ``dense``     -- an independent route: the global collocation system
                    assembled densely/sparsely and solved by a library LU.

@@ -9,7 +9,7 @@ u_c on every leaf and the value at every interior "master" Gauss node.  Rows:
 * E1 (collocated PDE, Sec. 3.2):  A(I_ci, :) u_c = g_ci on every leaf;
 * E2 (Gauss -> Chebyshev exterior, eq. alpine2p5):  u_c(I_ce) - L_ce,ge u_ge = 0,
   where u_ge holds f on the domain boundary and P_up times the coarse values
-  on refined, coarsened sides (Sec. 5.3);
+  on refined, coarsened sides (Sec. 6.3);
 * E3 (flux continuity, Sec. 4): at a Gauss node shared by two leaves the two
   leaf fluxes D_ge,c u_c agree; at a coarse node of a refined interface the
   coarse leaf's flux equals P_down applied to the fine leaves' fluxes.

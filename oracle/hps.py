@@ -1,14 +1,14 @@
 """Algorithms 1 and 2 with explicit per-box loops (oracle; test infrastructure).
 
-* ``build``  -- Algorithm 1 (Sec. 4.2): leaves by Sec. 3; parents by the merge
+* ``build``  -- Algorithm 1 (Sec. 5.2): leaves by Sec. 3; parents by the merge
   of Sec. 4: X = (T33a - T33b)^-1, S = X [-T31a | T32b],
   T = blkdiag(T11a, T22b) + [T13a; T23b] S.  A refined box whose side faces an
-  unrefined same-size leaf gets T <- P_down T P_up (Sec. 5.3); S is kept and
+  unrefined same-size leaf gets T <- P_down T P_up (Sec. 6.3); S is kept and
   P_up applied in the solve (S_new = S P_up).
-* ``solve``  -- Algorithm 2 (Sec. 4.3): upward pass h = H g at leaves,
+* ``solve``  -- Algorithm 2 (Sec. 5.3): upward pass h = H g at leaves,
   w = X(h3b - h3a), h = [h1a; h2b] + [T13a; T23b] w at parents (h <- P_down h
-  on coarsened boxes, Sec. 5.4); downward pass u(root boundary) = f,
-  u_gi = S u_ge + w at parents (u_ge,fine = P_up u_ge first, Sec. 5.4),
+  on coarsened boxes, Sec. 6.4); downward pass u(root boundary) = f,
+  u_gi = S u_ge + w at parents (u_ge,fine = P_up u_ge first, Sec. 6.4),
   u_c = S u_ge + F g at leaves.
 * ``solve_adjoint`` -- the transpose of the linear map (f, g) -> u_c of
   Algorithm 2, taken step by step in reverse order (not in the paper).

@@ -1,9 +1,9 @@
 """Box tree, Gauss node numbering and refinement (oracle; test infrastructure).
 
 Paper: Sec. 2 and Fig. 1 (binary tree of boxes, parent numbered before its
-children), Sec. 4.1 notation (global Gauss vector, I_ge / I_gi index vectors,
-J1/J2/J3 of the merge, Sec. 4 figure), Sec. 5.1 (refinement criterion) and
-Sec. 5.2-5.3 (neighbours, non-matching interfaces, P_up / P_down).
+children), Sec. 5.1 notation (global Gauss vector, I_ge / I_gi index vectors,
+J1/J2/J3 of the merge, Sec. 4 figure), Sec. 6.1 (refinement criterion) and
+Sec. 6.2-6.3 (neighbours, non-matching interfaces, P_up / P_down).
 
 Readings where the paper is silent:
 
@@ -17,9 +17,9 @@ Readings where the paper is silent:
 * Canonical leaf order for inputs and outputs: by (problem, y0, x0).
 * Canonical domain boundary order: sides S, E, N, W, increasing coordinate.
 * Refinement: a leaf splits into 2x2 when the distance from the target point
-  to the closed box is <= t * l, with 2l its side (Sec. 5.1).  A refined box
+  to the closed box is <= t * l, with 2l its side (Sec. 6.1).  A refined box
   whose same-size neighbour across a side is an unrefined leaf gets P_up /
-  P_down on that side (Sec. 5.3); a side with no same-size neighbour keeps its
+  P_down on that side (Sec. 6.3); a side with no same-size neighbour keeps its
   nodes.  P_up evaluates the coarse side's Gauss interpolant at every fine
   node; P_down evaluates, at each coarse node, the interpolant of the one fine
   panel containing it (the average of two panels on an exact junction).  With
@@ -84,7 +84,7 @@ class Tree:
         return x, y
 
     def refine_point(self, problem, px, py, n_ref, t=np.sqrt(2.0)):
-        """Sec. 5.1: n_ref rounds of splitting every close leaf into 2x2."""
+        """Sec. 6.1: n_ref rounds of splitting every close leaf into 2x2."""
         P = self.problems[problem]
         sx = (P["X1"] - P["X0"]) / (P["nx"] * U)
         sy = (P["Y1"] - P["Y0"]) / (P["ny"] * U)
@@ -259,7 +259,7 @@ class Tree:
         return xy, self._bdry
 
     def _coarsen(self, b, q, g, quads, nodes_of):
-        """Sec. 5.3: replace fine nodes on each side that faces an unrefined
+        """Sec. 6.3: replace fine nodes on each side that faces an unrefined
         same-size neighbour by that neighbour's q nodes; record P_up/P_down."""
         w, h = b.ix1 - b.ix0, b.iy1 - b.iy0
         segs = self._segs

@@ -125,6 +125,10 @@ struct hps_handle {
   int64_t ice_map = -1, ici_map = -1;
   int n_info = 0;
   bool has_fp32 = false;
+  // storage-economic build: leaf F not kept; the solve redoes the leaf
+  // Gauss-Jordan in chunks of econ_chunk leaves (econ_chunk = nleaf otherwise)
+  bool econ = false;
+  int econ_chunk = 0;
   std::vector<int64_t> off_T, off_X, off_S, off_LD, off_H;   // per box, -1 if absent
   int64_t scr_build = 0;          // scratch doubles the build needs
   // optional per-step timing (test hook): events around every launch step

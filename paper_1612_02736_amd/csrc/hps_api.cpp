@@ -363,7 +363,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   Lo.vec = pl.n_gauss;   // global u at the start of each RHS block
   H->ug_off = 0;
   for (int li : pl.leaves) {
-    Lo.LD[li] = ws_take(int64_t(mi) * (g4 + mi));
+    // [S_ci | F]; the economic build keeps S_ci only
+    Lo.LD[li] = ws_take(int64_t(mi) * (g4 + (H->econ ? 0 : mi)));
     Lo.H[li] = ws_take(int64_t(g4) * mi);
   }
   for (int b = 0; b < nb; ++b) {
@@ -443,6 +444,13 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     Lo.Aie_scr[li] = scr_take(int64_t(mi) * me);
     Lo.B_scr[li] = scr_take(int64_t(mi) * g4);
   }
+  // economic build: F of one chunk of leaves at a time (build and solve)
+  H->econ_chunk = H->econ ? std::min(nleaf, kEconChunk) : nleaf;
+  const int64_t f_scr = H->econ ? scr_take(int64_t(H->econ_chunk) * mi * mi) : -1;
+  auto f_ref = [&](int i) -> Ref {   // where leaf i's F lives
+    if (H->econ) return ref(BUF_SCR, f_scr + int64_t(i % H->econ_chunk) * mi * mi, mi);
+    return ref(BUF_WS, Lo.LD[pl.leaves[i]] + int64_t(g4) * mi, mi);
+  };
   for (int b = 0; b < nb; ++b) {
     const Box &B = pl.boxes[b];
     if (B.leaf) continue;
@@ -513,31 +521,33 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   // ======================= build program =======================
   auto &prog = H->build_prog;
   prog.clear();
-  // leaves: Gauss-Jordan
+  // leaves: Gauss-Jordan, then the leaf products, one chunk of leaves at a
+  // time (a single chunk unless the build is economic)
   for (int i = 0; i < nleaf; ++i) {
     const int li = pl.leaves[i];
     const auto &sc = pl.size_class[pl.leaf_class[i]];
     LeafDesc d{};
     d.coef = int64_t(i) * 6 * p * p;
-    d.F = Lo.LD[li] + int64_t(g4) * mi;
+    const Ref fr = f_ref(i);
+    d.F = fr.off;
+    d.fbuf = fr.buf;
     d.Aie = Lo.Aie_scr[li];
     d.sx = 2.0 / sc.first;
     d.sy = 2.0 / sc.second;
     d.info = i;
     leafd.push_back(d);
   }
-  {
+  for (int c0 = 0; c0 < nleaf; c0 += H->econ_chunk) {
+    const int c1 = std::min(nleaf, c0 + H->econ_chunk);
     Step s{S_GJ_LEAF};
-    s.d0 = 0;
-    s.nd = nleaf;
+    s.d0 = c0;
+    s.nd = c1 - c0;
     prog.push_back(s);
-  }
-  {
     GemmList a, b2, c;
-    for (int i = 0; i < nleaf; ++i) {
+    for (int i = c0; i < c1; ++i) {
       const int li = pl.leaves[i];
       const int role = pl.boxes[li].role, cls = pl.leaf_class[i];
-      const int64_t F = Lo.LD[li] + int64_t(g4) * mi;
+      const Ref F = f_ref(i);
       const int64_t Dci = Lo.Dci[size_t(cls) * 5 + role], T0 = Lo.T0[size_t(cls) * 5 + role];
       GemmDesc g{};
       // B = A_ci,ce L
@@ -550,14 +560,14 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       // H = D_ge,ci F
       g = GemmDesc{};
       g.M = g4; g.N = mi; g.K = mi;
-      g.A = ref(BUF_WS, Dci, g4); g.B = ref(BUF_WS, F, mi);
+      g.A = ref(BUF_WS, Dci, g4); g.B = F;
       g.C = ref(BUF_WS, Lo.H[li], g4); g.D = noref();
       g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
       a.add(g);
       // S_ci = -F B
       g = GemmDesc{};
       g.M = mi; g.N = g4; g.K = mi;
-      g.A = ref(BUF_WS, F, mi); g.B = ref(BUF_SCR, Lo.B_scr[li], mi);
+      g.A = F; g.B = ref(BUF_SCR, Lo.B_scr[li], mi);
       g.C = ref(BUF_WS, Lo.LD[li], mi); g.D = noref();
       g.crow = g.ccol = -1; g.alpha = -1.0; g.beta = 0.0;
       b2.add(g);
@@ -692,6 +702,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       a.ksl = std::max(1, std::min(64, (K + 511) / 512));
       a.ksl = std::max(a.ksl, std::min(want, std::max(1, K / 64)));
       a.ksl = std::min(a.ksl, 64);
+      if (a.abuf == BUF_SCR) a.ksl = 1;   // split-K partials live in BUF_SCR too
       a.tile0 = tiles;
       tiles += int64_t(a.rb) * a.ksl;
       appl_tmap.insert(appl_tmap.end(), size_t(int64_t(a.rb) * a.ksl),
@@ -808,9 +819,10 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     for (int i = 0; i < nleaf; ++i) {
       const int li = pl.leaves[i];
       const int role = pl.boxes[li].role;
-      ApplyDesc a = ad(mi, g4, mi, 0, Lo.LD[li], mi);
+      // u_ci = [S_ci | F] [u_ge; g] (economic: S_ci u_ge, F g added below)
+      ApplyDesc a = ad(mi, g4, H->econ ? 0 : mi, 0, Lo.LD[li], mi);
       a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[li], kInterleaved);
-      a.B2 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
+      if (!H->econ) a.B2 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
       a.C = vref(BUF_IN2, int64_t(i) * p * p, H->ici_map, ustride);
       tmp.push_back(a);
       ApplyDesc e = ad(me, g4, 0, 0, Lo.L_role[role], me);
@@ -819,6 +831,34 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       tmp.push_back(e);
     }
     apply_step(tmp, dn);
+    if (H->econ) {
+      // the storage-economic solve: per chunk of leaves, the leaf
+      // Gauss-Jordan again (F into the chunk scratch, A_ci,ce not written),
+      // then u_ci += F g
+      for (int i = 0; i < nleaf; ++i) {
+        LeafDesc d = leafd[i];
+        d.Aie = -1;
+        leafd.push_back(d);
+      }
+      for (int c0 = 0; c0 < nleaf; c0 += H->econ_chunk) {
+        const int c1 = std::min(nleaf, c0 + H->econ_chunk);
+        Step s{S_GJ_LEAF};
+        s.d0 = nleaf + c0;
+        s.nd = c1 - c0;
+        dn.push_back(s);
+        for (int i = c0; i < c1; ++i) {
+          const Ref F = f_ref(i);
+          ApplyDesc a = ad(mi, mi, 0, 0, F.off, mi);
+          a.abuf = F.buf;
+          a.B1 = vref(BUF_IN1, int64_t(i) * mi, -1, gstride);
+          a.C = vref(BUF_IN2, int64_t(i) * p * p, H->ici_map, ustride);
+          a.D = a.C;
+          a.beta = 1.0;
+          tmp.push_back(a);
+        }
+        apply_step(tmp, dn);
+      }
+    }
   }
   // transposed applies of the adjoint use the same descriptor layout
   auto apply_step_t = [&](std::vector<ApplyDesc> &tmp, std::vector<Step> &prg) {
@@ -886,10 +926,12 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       b.beta = 1.0;
       b.C = vref(BUF_VEC, Lo.Ub[li], -1, kInterleaved);
       t2.push_back(b);
-      ApplyDesc c = ad(mi, mi, 0, 0, Lo.LD[li] + int64_t(g4) * mi, mi);   // F^T ubar(I_ci)
-      c.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ici_map, ustride);
-      c.C = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
-      t2.push_back(c);
+      if (!H->econ) {                 // the adjoint needs the stored F
+        ApplyDesc c = ad(mi, mi, 0, 0, Lo.LD[li] + int64_t(g4) * mi, mi);   // F^T ubar(I_ci)
+        c.B1 = vref(BUF_IN0, int64_t(i) * p * p, H->ici_map, ustride);
+        c.C = vref(BUF_IN2, int64_t(i) * mi, -1, gstride);
+        t2.push_back(c);
+      }
     }
     apply_step_t(t1, P);
     apply_step_t(t2, P);
@@ -1083,6 +1125,7 @@ Bases make_bases(hps_handle *H) {
   b.d[BUF_VEC] = H->vec.p;
   b.d[BUF_W32] = H->ws32.p;
   b.d[BUF_AUX] = H->aux.p;
+  b.d[BUF_COEF] = H->coef.p;
   b.imap = H->imap.p;
   b.iota = H->imap.p ? H->imap.p + H->iota_off : nullptr;
   return b;
@@ -1188,10 +1231,15 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
 extern "C" {
 
 size_t hps_build_workspace_size(const hps_tree *tree, int p, int q) {
+  return hps_build_workspace_size_econ(tree, p, q, 0);
+}
+
+size_t hps_build_workspace_size_econ(const hps_tree *tree, int p, int q, int economic) {
   if (!tree || p < 4) return 0;
   if (q <= 0) q = p - 1;
   hps_handle H;
   H.tree = tree->t;
+  H.econ = economic != 0;
   if (plan_tree(H.tree, H.pl, q)) return 0;
   H.p = p; H.q = q; H.mi = (p - 2) * (p - 2); H.me = 4 * (p - 1); H.g4 = 4 * q;
   H.nleaf = (int)H.pl.leaves.size();
@@ -1218,10 +1266,13 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   int q = opts && opts->q > 0 ? opts->q : p - 1;
   if (p < 4 || q < 2 || q >= p) return fail(HPS_EINVAL, "need p >= 4 and 2 <= q < p");
   if (!gj_leaf_supported(p)) return fail(HPS_EINVAL, "p must be one of 6, 8, 10, 12, 16");
+  if (opts && opts->economic && opts->keep_fp32)
+    return fail(HPS_EINVAL, "economic builds keep no leaf operators to copy to FP32");
   hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
   std::unique_ptr<hps_handle> H(new (std::nothrow) hps_handle);
   if (!H) return fail(HPS_ENOMEM, "host allocation");
   H->tree = tree->t;
+  H->econ = opts && opts->economic;
   int rc = plan_tree(H->tree, H->pl, q);
   if (rc) return rc;
   H->p = p; H->q = q; H->mi = (p - 2) * (p - 2); H->me = 4 * (p - 1); H->g4 = 4 * q;
@@ -1276,7 +1327,6 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   HIPCHK(H->coef.alloc(ncoef));
   HIPCHK(hipMemcpyAsync(H->coef.p, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, st));
   Bases bs = make_bases(H.get());
-  bs.d[BUF_IN0] = (void *)coeffs;
   rc = run_prog(H.get(), H->build_prog, bs, 1, 0, st);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
@@ -1313,8 +1363,7 @@ int hps_refactor(hps_handle *H, const double *coeffs, void *stream) {
   HIPCHK(hipMemsetAsync(H->info.p, 0, sizeof(int32_t) * H->n_info, st));
   const size_t ncoef = size_t(H->nleaf) * 6 * H->p * H->p;
   HIPCHK(hipMemcpyAsync(H->coef.p, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, st));
-  Bases bs = make_bases(H);
-  bs.d[BUF_IN0] = H->coef.p;          // the handle's copy: fixed address for the graph
+  Bases bs = make_bases(H);           // coefficients: the handle's copy (fixed address)
   int rc = HPS_OK;
   if (H->prof_on) {
     rc = run_prog(H, H->build_prog, bs, 1, 0, st);   // per-launch events need eager launches

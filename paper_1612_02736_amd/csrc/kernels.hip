@@ -412,7 +412,7 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
   const int leaf = blockIdx.x;
   if (leaf >= nleaf) return;
   const LeafDesc &d = descs[leaf];
-  const double *coef = (const double *)bs.d[BUF_IN0] + d.coef;
+  const double *coef = (const double *)bs.d[BUF_COEF] + d.coef;
   const int tid = threadIdx.x;
   for (int i = tid; i < 6 * P * P; i += blockDim.x) cf[i / (P * P)][i % (P * P)] = coef[i];
   for (int i = tid; i < P * P; i += blockDim.x) { Dh[i] = Dh_g[i]; Dh2[i] = Dh2_g[i]; }
@@ -429,10 +429,12 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
   };
   auto grid_of = [](int a) { const int y = a / PI; return (y + 1) * P + (a - y * PI) + 1; };
   // A_ci,ce (mi x me, column-major) for the leaf products
-  double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
-  for (int idx = tid; idx < MI * me; idx += blockDim.x) {
-    const int a = idx % MI, e = idx / MI;
-    Aie[idx] = entry(grid_of(a), ice[e]);
+  if (d.Aie >= 0) {
+    double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
+    for (int idx = tid; idx < MI * me; idx += blockDim.x) {
+      const int a = idx % MI, e = idx / MI;
+      Aie[idx] = entry(grid_of(a), ice[e]);
+    }
   }
   int tr, tc;
   gj_owner<TR, TC, RA, CB>(tid, tr, tc);
@@ -447,7 +449,7 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
     }
   }
   gj_core<TR, TC, RA, CB>(a, MI, tr, tc, sh);
-  double *F = (double *)bs.d[BUF_WS] + d.F;
+  double *F = (double *)bs.d[d.fbuf] + d.F;
   gj_store<TR, TC, RA, CB>(a, MI, tr, tc, sh, F, MI);
   if (tid == 0) info[d.info] = sh.info;
 }
@@ -705,7 +707,7 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
   const int leaf = blockIdx.x;
   if (leaf >= nleaf) return;
   const LeafDesc &d = descs[leaf];
-  const double *coef = (const double *)bs.d[BUF_IN0] + d.coef;
+  const double *coef = (const double *)bs.d[BUF_COEF] + d.coef;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int i = tid; i < 6 * P * P; i += NW * 64) cf[i / (P * P)][i % (P * P)] = coef[i];
   for (int i = tid; i < P * P; i += NW * 64) { Dh[i] = Dh_g[i]; Dh2[i] = Dh2_g[i]; }
@@ -720,10 +722,12 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
     return v;
   };
   auto grid_of = [](int a) { const int y = a / PI; return (y + 1) * P + (a - y * PI) + 1; };
-  double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
-  for (int idx = tid; idx < MI * me; idx += NW * 64) {
-    const int a = idx % MI, e = idx / MI;
-    Aie[idx] = entry(grid_of(a), ice[e]);
+  if (d.Aie >= 0) {             // A_ci,ce for the leaf products
+    double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
+    for (int idx = tid; idx < MI * me; idx += NW * 64) {
+      const int a = idx % MI, e = idx / MI;
+      Aie[idx] = entry(grid_of(a), ice[e]);
+    }
   }
   double a[RA][CB];
 #pragma unroll
@@ -736,7 +740,7 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
     }
   }
   gj2_core<NW, RA, CB>(a, MI, lane, wid, sh);
-  double *F = (double *)bs.d[BUF_WS] + d.F;
+  double *F = (double *)bs.d[d.fbuf] + d.F;
 #pragma unroll
   for (int i = 0; i < RA; ++i) {
     const int row = lane + 64 * i;

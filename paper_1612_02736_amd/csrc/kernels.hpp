@@ -13,6 +13,8 @@ constexpr int kPanelNBMax = 32;   // widest panel of the blocked Gauss-Jordan
 int panel_nb(int maxm);           // panel width used for a level of size maxm
 
 // tmap[t] = index (into descs) of the descriptor that owns tile t
+// leaves per chunk of the storage-economic build and solve
+constexpr int kEconChunk = 1024;
 // info code of a leaf Gauss-Jordan whose flag-synchronised sweep gave up
 // waiting (never in a correct run)
 constexpr int kGjSyncTimeout = -0x7fffffff;

@@ -228,7 +228,7 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
       cur.assign(A.fin.begin(), A.fin.end() - m);
       cur.insert(cur.end(), B.fin.begin(), B.fin.end() - m);
       b.nat = cur;
-      // Sec. 5.3: coarsen sides facing an unrefined same-size leaf
+      // Sec. 6.3: coarsen sides facing an unrefined same-size leaf
       const bool quadbox = b.kind == 1 ||
                            (b.kind == 0 && b.ix1 - b.ix0 == kUnit && b.iy1 - b.iy0 == kUnit);
       if (quadbox) {

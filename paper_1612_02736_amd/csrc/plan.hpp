@@ -2,8 +2,8 @@
 // interface operators and the device workspace layout.
 //
 // Paper: Sec. 2 / Fig. 1 (binary tree, parent before child), Sec. 4 and its
-// figure (J1, J2, J3), Sec. 4.1 (global Gauss vector), Sec. 5.1 (refinement
-// criterion), Sec. 5.2-5.4 (neighbours, P_up / P_down).
+// figure (J1, J2, J3), Sec. 5.1 (global Gauss vector), Sec. 6.1 (refinement
+// criterion), Sec. 6.2-6.4 (neighbours, P_up / P_down).
 //
 // Orders used on the device (all matrices column-major):
 //  * a box's "natural" boundary order: leaf S,E,N,W; parent J1 then J2;

@@ -17,7 +17,8 @@ enum BufId : int32_t {
   BUF_VEC = 5,    // per-solve work vectors (h / w slots, global u, residuals)
   BUF_W32 = 6,    // FP32 operator copies
   BUF_AUX = 7,
-  NBUF = 8
+  BUF_COEF = 8,   // the handle's copy of the nodal coefficients
+  NBUF = 9
 };
 
 struct Bases {
@@ -45,12 +46,12 @@ struct GemmDesc {
 // Leaf interior block: assemble A_ci,ci and A_ci,ce from the nodal
 // coefficients, invert A_ci,ci in place (Gauss-Jordan, partial pivoting).
 struct LeafDesc {
-  int64_t coef;   // BUF_IN0 offset of the leaf's [6][p*p] coefficients
-  int64_t F;      // BUF_WS offset of F (mi x mi, ld mi)
-  int64_t Aie;    // BUF_SCR offset of A_ci,ce (mi x me, ld mi)
+  int64_t coef;   // BUF_COEF offset of the leaf's [6][p*p] coefficients
+  int64_t F;      // offset of F (mi x mi, ld mi) in buffer fbuf
+  int64_t Aie;    // BUF_SCR offset of A_ci,ce (mi x me, ld mi); < 0: not written
   double sx, sy;  // 2/hx, 2/hy
   int32_t info;   // slot in the info array
-  int32_t pad;
+  int32_t fbuf;   // buffer of F: BUF_WS (stored) or BUF_SCR (recomputed per chunk)
 };
 
 // Interface block of a merge: X = (T33a - T33b)^-1.

@@ -89,3 +89,33 @@ def test_workspace_size_grows_with_tree():
     # leaves alone: F, S_ci, H, T in FP64
     mi, g4 = 14 * 14, 60
     assert b >= 64 * 8 * (mi * (mi + g4) + g4 * mi + g4 * g4)
+
+
+def test_economic_workspace_drops_exactly_the_leaf_inverses():
+    """The storage-efficient version (Sec. 5.4 remark) keeps no leaf F: each
+    leaf's [S_ci | F] block (mi x (4q + mi) doubles) shrinks to S_ci (mi x 4q),
+    blocks being padded to 32 doubles, on uniform and refined trees and for
+    several p."""
+    H = _H()
+    pad = lambda n: (n + 31) // 32 * 32
+    for (nx, p, refine) in [(4, 16, None), (8, 12, None), (4, 10, (0.3, 0.6, 2))]:
+        t = H.Tree(0, 1, 0, 1, nx, nx)
+        if refine:
+            t.refine_point(0, *refine)
+        mi, g4 = (p - 2) ** 2, 4 * (p - 1)
+        full, econ = t.workspace_bytes(p), t.workspace_bytes(p, economic=True)
+        assert full - econ == 8 * t.n_leaves * (pad(mi * (g4 + mi)) - pad(mi * g4)), \
+            (nx, p, full, econ)
+        assert full - econ >= 8 * t.n_leaves * (mi * mi - 32)
+
+
+def test_economic_build_rejects_fp32_copies():
+    H = _H()
+    L = H.lib()
+    t = H.Tree(0, 1, 0, 1, 2, 2)
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)          # never dereferenced: arguments fail first
+    o = H.hps.BuildOpts(q=0, stream=None, keep_fp32=1, economic=1)
+    assert L.hps_build(t._h, fake, 8, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert not out.value
+    assert "economic" in L.hps_last_error().decode()

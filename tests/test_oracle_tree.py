@@ -1,5 +1,5 @@
 """Pins for the oracle's tree, merge and full solve (Sec. 4, Algorithms 1-2,
-Sec. 5): brute force against the global collocation system, exactness on
+Sec. 6): brute force against the global collocation system, exactness on
 harmonic and on arbitrary low-degree polynomials, the physical meaning of the
 merge, split-order invariance, refinement counts and spectral convergence."""
 
@@ -113,7 +113,7 @@ def test_split_order_invariance():
 
 
 def test_merge_particular_solution_meaning():
-    """Sec. 4 remark: w_gi of a parent equals the zero-Dirichlet particular
+    """Sec. 5.3 remark: w_gi of a parent equals the zero-Dirichlet particular
     solution of that parent box on its interior edge; computed here by the
     global collocation system posed on the parent box alone."""
     p, q = 10, 9
@@ -167,7 +167,7 @@ def test_refined_tree_matches_dense_and_reproduces_polynomials(base, pt, nref, p
 
 
 def test_two_panel_interface_operators_are_paper_blocks():
-    """Sec. 5.3: for a side with 2q fine nodes against q coarse ones, P_down
+    """Sec. 6.3: for a side with 2q fine nodes against q coarse ones, P_down
     is two q/2 x q blocks (q even) and P_up reproduces the coarse data."""
     p, q = 9, 8
     t = oracle.Tree.uniform(0, 1, 0, 1, 2, 2)
