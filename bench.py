@@ -207,6 +207,18 @@ def main():
         solver.solve_adjoint(ub)
     torch.cuda.synchronize()
     adj_ms = (time.perf_counter() - a0) * 1e3 / 3
+    # storage-economic version (leaf F not stored, recomputed by every solve)
+    se = H.Solver(tree, cd, P, Q, economic=True)
+    ue = se.solve(fd, gd)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(3):
+        ue = se.solve(fd, gd)
+    torch.cuda.synchronize()
+    econ_ms = (time.perf_counter() - e0) * 1e3 / 3
+    econ_diff = float((ue - u).abs().max() / u.abs().max())
+    del se, ue
+    ws_full, ws_econ = tree.workspace_bytes(P, Q), tree.workspace_bytes(P, Q, economic=True)
     # accuracy against stored oracle values (seed 2 = right-hand side 0)
     rel_err = rel_err_mixed = None
     ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
@@ -284,6 +296,11 @@ def main():
         "adjoint_ms_nrhs32": adj_ms,
         "adjoint_over_forward": adj_ms / solve32_ms,
         "solve_operator_gb": fm["solve_bytes"] / 1e9,
+        "economic_solve_ms_nrhs32": econ_ms,
+        "economic_over_stored_solve": econ_ms / solve32_ms,
+        "economic_rel_diff_vs_stored": econ_diff,
+        "operator_gb_stored": ws_full / 1e9,
+        "operator_gb_economic": ws_econ / 1e9,
         "rel_err_vs_oracle": rel_err,
         "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},

@@ -78,6 +78,16 @@ typedef struct {
                             in chunks of 1024 leaves to apply F g.  Removes
                             the N q^2 storage term; FP64 forward solves only
                             (no keep_fp32, no adjoint). */
+  int translation_invariant; /* 1: the coefficients are the same on every
+                            leaf (a constant-coefficient operator on a tree
+                            without refined interfaces; the remark after the
+                            timings of Sec. 7.1): leaves, and merges within a
+                            level, that have the same shape and position in
+                            their parent get one shared copy of their
+                            operators, built once.  hps_build and
+                            hps_refactor check the coefficients on the host
+                            and return HPS_EINVAL if they differ between
+                            leaves; not combined with economic. */
 } hps_build_opts;
 
 enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
@@ -158,6 +168,10 @@ size_t hps_build_workspace_size(const hps_tree *tree, int p, int q);
 
 /* The same for a build with hps_build_opts.economic = economic. */
 size_t hps_build_workspace_size_econ(const hps_tree *tree, int p, int q, int economic);
+
+/* The same with hps_build_opts.economic and .translation_invariant. */
+size_t hps_build_workspace_size_opts(const hps_tree *tree, int p, int q, int economic,
+                                     int translation_invariant);
 
 /* -- solve stage (Algorithm 2) -------------------------------------------- */
 

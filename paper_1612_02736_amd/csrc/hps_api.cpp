@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -359,10 +360,40 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     std::vector<int32_t> w(v.begin(), v.end());
     return imap_put(w);
   };
+  // Translation-invariant operators (constant coefficients, the remark after
+  // the timings of Sec. 7.1): boxes with the same key -- a leaf's size class
+  // and role, a merge's children's keys, cut, role and final order -- have
+  // identical operators, stored once at the key's first box (rep).
+  std::vector<int> rep(nb);
+  for (int b = 0; b < nb; ++b) rep[b] = b;
+  if (H->dedup) {
+    std::map<std::vector<int64_t>, int> first;
+    std::vector<int64_t> kid(nb, -1);
+    for (int b = nb - 1; b >= 0; --b) {       // children come after their parent
+      const Box &B = pl.boxes[b];
+      std::vector<int64_t> k;
+      if (B.leaf) {
+        k = {0, pl.leaf_class[B.leaf_index], B.role};
+      } else {
+        k = {1, kid[B.alpha], kid[B.beta], B.cut, B.role, B.n_shared, (int64_t)B.gi.size()};
+        k.insert(k.end(), B.pi.begin(), B.pi.end());
+      }
+      auto it = first.find(k);
+      if (it == first.end()) {
+        kid[b] = (int64_t)first.size();
+        first.emplace(k, b);
+      } else {
+        kid[b] = kid[it->second];
+        rep[b] = it->second;
+      }
+    }
+  }
+  auto own = [&](int b) { return rep[b] == b; };
   // --- solve-stage operators first (they are the FP32-copied prefix) ---
   Lo.vec = pl.n_gauss;   // global u at the start of each RHS block
   H->ug_off = 0;
   for (int li : pl.leaves) {
+    if (!own(li)) continue;
     // [S_ci | F]; the economic build keeps S_ci only
     Lo.LD[li] = ws_take(int64_t(mi) * (g4 + (H->econ ? 0 : mi)));
     Lo.H[li] = ws_take(int64_t(g4) * mi);
@@ -370,6 +401,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   for (int b = 0; b < nb; ++b) {
     const Box &B = pl.boxes[b];
     const int ef = (int)B.fin.size();
+    if (!own(b)) continue;
     if (B.parent >= 0) Lo.T[b] = ws_take(int64_t(ef) * ef);
     if (!B.leaf) {
       const int m = (int)B.gi.size(), en = (int)B.nat.size();
@@ -382,6 +414,12 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       }
     }
   }
+  for (int b = 0; b < nb; ++b)
+    if (!own(b)) {
+      const int r = rep[b];
+      Lo.LD[b] = Lo.LD[r]; Lo.H[b] = Lo.H[r]; Lo.T[b] = Lo.T[r];
+      Lo.X[b] = Lo.X[r]; Lo.S[b] = Lo.S[r];
+    }
   // reference matrices per role / size class
   LeafRef R = leaf_reference(p, q);
   Lo.L_role.assign(5, -1);
@@ -440,10 +478,13 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   // leaf temporaries and T
   for (int i = 0; i < nleaf; ++i) {
     const int li = pl.leaves[i];
+    if (!own(li)) continue;
     if (Lo.T[li] < 0) Lo.T[li] = ws_take(int64_t(g4) * g4);   // single-leaf root
     Lo.Aie_scr[li] = scr_take(int64_t(mi) * me);
     Lo.B_scr[li] = scr_take(int64_t(mi) * g4);
   }
+  for (int li : pl.leaves)
+    if (!own(li)) Lo.T[li] = Lo.T[rep[li]];
   // economic build: F of one chunk of leaves at a time (build and solve)
   H->econ_chunk = H->econ ? std::min(nleaf, kEconChunk) : nleaf;
   const int64_t f_scr = H->econ ? scr_take(int64_t(H->econ_chunk) * mi * mi) : -1;
@@ -453,7 +494,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   };
   for (int b = 0; b < nb; ++b) {
     const Box &B = pl.boxes[b];
-    if (B.leaf) continue;
+    if (B.leaf || !own(b)) continue;
     const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
     if (gj_merge_class(m) < 0) {
       Lo.W_scr[b] = scr_take(std::max<int64_t>(int64_t(kPanelNBMax) * m, int64_t(m) * m));
@@ -537,14 +578,26 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     d.info = i;
     leafd.push_back(d);
   }
-  for (int c0 = 0; c0 < nleaf; c0 += H->econ_chunk) {
-    const int c1 = std::min(nleaf, c0 + H->econ_chunk);
+  // the leaves whose operators the build computes (all but deduplicated
+  // ones); their descriptors follow the per-leaf list when that is a subset
+  std::vector<int> bl;
+  for (int i = 0; i < nleaf; ++i)
+    if (own(pl.leaves[i])) bl.push_back(i);
+  const int nbl = (int)bl.size();
+  int64_t bl0 = 0;
+  if (nbl < nleaf) {
+    bl0 = (int64_t)leafd.size();
+    for (int i : bl) leafd.push_back(leafd[i]);
+  }
+  for (int c0 = 0; c0 < nbl; c0 += H->econ_chunk) {
+    const int c1 = std::min(nbl, c0 + H->econ_chunk);
     Step s{S_GJ_LEAF};
-    s.d0 = c0;
+    s.d0 = bl0 + c0;
     s.nd = c1 - c0;
     prog.push_back(s);
     GemmList a, b2, c;
-    for (int i = c0; i < c1; ++i) {
+    for (int ci = c0; ci < c1; ++ci) {
+      const int i = bl[ci];
       const int li = pl.leaves[i];
       const int role = pl.boxes[li].role, cls = pl.leaf_class[i];
       const Ref F = f_ref(i);
@@ -588,7 +641,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   for (int h = 1; h <= pl.max_height; ++h) {
     std::vector<int> lev;
     for (int b = 0; b < nb; ++b)
-      if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
+      if (!pl.boxes[b].leaf && pl.boxes[b].height == h && own(b)) lev.push_back(b);
     if (lev.empty()) continue;
     std::vector<MergeInvDesc> levd;
     for (int b : lev) {
@@ -1230,17 +1283,40 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
 
 extern "C" {
 
+// Host check that every leaf has the coefficients of leaf 0 (translation
+// invariant builds share operators between leaves).
+static int check_constant_coeffs(const double *coeffs, int nleaf, int p) {
+  const size_t per = size_t(6) * p * p;
+  std::vector<double> h(per * nleaf);
+  HIPCHK(hipMemcpy(h.data(), coeffs, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 1; i < nleaf; ++i)
+    if (std::memcmp(&h[per * i], h.data(), per * sizeof(double)) != 0)
+      return fail(HPS_EINVAL, "translation_invariant: the coefficients of leaf " +
+                                  std::to_string(i) + " differ from leaf 0");
+  return HPS_OK;
+}
+
 size_t hps_build_workspace_size(const hps_tree *tree, int p, int q) {
   return hps_build_workspace_size_econ(tree, p, q, 0);
 }
 
 size_t hps_build_workspace_size_econ(const hps_tree *tree, int p, int q, int economic) {
+  return hps_build_workspace_size_opts(tree, p, q, economic, 0);
+}
+
+size_t hps_build_workspace_size_opts(const hps_tree *tree, int p, int q, int economic,
+                                     int translation_invariant) {
   if (!tree || p < 4) return 0;
   if (q <= 0) q = p - 1;
   hps_handle H;
   H.tree = tree->t;
   H.econ = economic != 0;
+  H.dedup = translation_invariant != 0;
+  if (H.econ && H.dedup) return 0;
   if (plan_tree(H.tree, H.pl, q)) return 0;
+  if (H.dedup)
+    for (const Box &b : H.pl.boxes)
+      if (b.coarsened) return 0;
   H.p = p; H.q = q; H.mi = (p - 2) * (p - 2); H.me = 4 * (p - 1); H.g4 = 4 * q;
   H.nleaf = (int)H.pl.leaves.size();
   Layout Lo;
@@ -1273,13 +1349,23 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   if (!H) return fail(HPS_ENOMEM, "host allocation");
   H->tree = tree->t;
   H->econ = opts && opts->economic;
+  H->dedup = opts && opts->translation_invariant;
+  if (H->econ && H->dedup)
+    return fail(HPS_EINVAL, "economic and translation_invariant builds do not combine");
   int rc = plan_tree(H->tree, H->pl, q);
   if (rc) return rc;
   H->p = p; H->q = q; H->mi = (p - 2) * (p - 2); H->me = 4 * (p - 1); H->g4 = 4 * q;
   H->nleaf = (int)H->pl.leaves.size();
-  for (const Box &b : H->pl.boxes)
+  for (const Box &b : H->pl.boxes) {
     if (!b.leaf && (int)b.gi.size() > 2048)
       return fail(HPS_EINVAL, "interface longer than 2048 nodes");
+    if (H->dedup && b.coarsened)
+      return fail(HPS_EINVAL, "translation_invariant builds need a tree without refined interfaces");
+  }
+  if (H->dedup) {
+    rc = check_constant_coeffs(coeffs, H->nleaf, p);
+    if (rc) return rc;
+  }
   Layout Lo;
   std::vector<double> aux_init;
   std::vector<std::pair<int64_t, std::vector<double>>> blocks;
@@ -1359,6 +1445,10 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
 int hps_refactor(hps_handle *H, const double *coeffs, void *stream) {
   if (!H || !coeffs) return fail(HPS_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
+  if (H->dedup) {
+    const int rc0 = check_constant_coeffs(coeffs, H->nleaf, H->p);
+    if (rc0) return rc0;
+  }
   if (H->scr.n < size_t(H->scr_build)) HIPCHK(H->scr.alloc(H->scr_build));
   HIPCHK(hipMemsetAsync(H->info.p, 0, sizeof(int32_t) * H->n_info, st));
   const size_t ncoef = size_t(H->nleaf) * 6 * H->p * H->p;

@@ -22,7 +22,7 @@ EXPORTS = ["hps_tree_uniform", "hps_tree_refine_point", "hps_tree_info",
            "hps_tree_counts", "hps_leaf_cheb_nodes", "hps_leaf_boxes",
            "hps_bdry_gauss_nodes", "hps_gauss_nodes", "hps_tree_free",
            "hps_build", "hps_refactor", "hps_build_workspace_size",
-           "hps_build_workspace_size_econ", "hps_solve",
+           "hps_build_workspace_size_econ", "hps_build_workspace_size_opts", "hps_solve",
            "hps_solve_adjoint", "hps_coeff_grad_c", "hps_handle_free",
            "hps_last_error"]
 
@@ -41,7 +41,8 @@ class TreeInfo(ctypes.Structure):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("keep_fp32", ctypes.c_int), ("economic", ctypes.c_int)]
+                ("keep_fp32", ctypes.c_int), ("economic", ctypes.c_int),
+                ("translation_invariant", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -80,6 +81,8 @@ def lib():
     L.hps_build_workspace_size.restype = ctypes.c_size_t
     L.hps_build_workspace_size_econ.argtypes = [vp, ip, ip, ip]
     L.hps_build_workspace_size_econ.restype = ctypes.c_size_t
+    L.hps_build_workspace_size_opts.argtypes = [vp, ip, ip, ip, ip]
+    L.hps_build_workspace_size_opts.restype = ctypes.c_size_t
     L.hps_solve.argtypes = [vp, vp, vp, ip, vp, ctypes.POINTER(SolveOpts)]
     L.hps_solve_adjoint.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(SolveOpts)]
     L.hps_coeff_grad_c.argtypes = [vp, vp, vp, ip, vp, vp]
@@ -162,10 +165,12 @@ class Tree:
         _check(lib().hps_gauss_nodes(self._h, q, _np_ptr(out)))
         return out
 
-    def workspace_bytes(self, p, q=0, economic=False):
+    def workspace_bytes(self, p, q=0, economic=False, translation_invariant=False):
         """Device bytes of the operators a build stores (economic: without
-        the leaf F, the storage-efficient version of Sec. 5.4)."""
-        return lib().hps_build_workspace_size_econ(self._h, p, q, int(economic))
+        the leaf F, the storage-efficient version of Sec. 5.4;
+        translation_invariant: one copy per distinct box)."""
+        return lib().hps_build_workspace_size_opts(self._h, p, q, int(economic),
+                                                   int(translation_invariant))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -176,7 +181,8 @@ class Tree:
 class Solver:
     """Handle of a built solution operator (Algorithm 1)."""
 
-    def __init__(self, tree, coeffs, p, q=0, keep_fp32=False, economic=False, stream=None):
+    def __init__(self, tree, coeffs, p, q=0, keep_fp32=False, economic=False,
+                 translation_invariant=False, stream=None):
         import torch
         self.tree, self.p = tree, p
         self.q = q if q > 0 else p - 1
@@ -185,7 +191,8 @@ class Solver:
         if tuple(coeffs.shape) != (self.n_leaves, 6, p * p):
             raise ValueError(f"coeffs must be [{self.n_leaves}, 6, {p * p}]")
         o = BuildOpts(q=self.q, stream=_stream(stream), keep_fp32=int(keep_fp32),
-                      economic=int(economic))
+                      economic=int(economic),
+                      translation_invariant=int(translation_invariant))
         h = ctypes.c_void_p()
         _check(lib().hps_build(tree._h, _dev_ptr(coeffs, "coeffs"), p, ctypes.byref(o),
                                ctypes.byref(h)))

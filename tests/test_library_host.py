@@ -119,3 +119,18 @@ def test_economic_build_rejects_fp32_copies():
     assert L.hps_build(t._h, fake, 8, ctypes.byref(o), ctypes.byref(out)) == -1
     assert not out.value
     assert "economic" in L.hps_last_error().decode()
+
+
+def test_translation_invariant_workspace():
+    """One operator copy per distinct box: far below the full build on
+    uniform trees, never above it, and not offered on refined trees."""
+    H = _H()
+    for (nx, p) in [(4, 16), (16, 12), (64, 16)]:
+        t = H.Tree(0, 1, 0, 1, nx, nx)
+        full, ded = t.workspace_bytes(p), t.workspace_bytes(p, translation_invariant=True)
+        assert 0 < ded <= full, (nx, p, ded, full)
+        if nx >= 16:
+            assert ded < full / 4, (nx, p, ded, full)
+    t = H.Tree(0, 1, 0, 1, 4, 4).refine_point(0, 0.3, 0.6, 2)
+    assert t.workspace_bytes(12, translation_invariant=True) == 0
+    assert t.workspace_bytes(12, economic=True, translation_invariant=True) == 0
