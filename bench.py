@@ -113,6 +113,43 @@ def cpu_baseline(nrhs):
             "factor_s_scaled": t_build, "solve_s_scaled": t_solve}
 
 
+def translation_invariant_case(H, torch, dev, nrhs, reps=3):
+    """(I - dt Lap) u = g on 128 x 128 leaves, p = 12: factor and 32-RHS
+    solve times of the full build and of the translation-invariant one."""
+    import workloads as W
+    n, p, q = 128, 12, 11
+    t = H.Tree(0.0, 1.0, 0.0, 1.0, n, n)
+    xy = t.leaf_cheb_nodes(p)
+    coeffs = np.stack([W.heat_coeffs(xy[i, :, 0], xy[i, :, 1]) for i in range(t.n_leaves)])
+    rng = np.random.default_rng(3)
+    ng, nb = t.counts(q)
+    cd = torch.from_numpy(coeffs).to(dev)
+    fd = torch.from_numpy(rng.standard_normal((nrhs, nb))).to(dev)
+    gd = torch.from_numpy(rng.standard_normal((nrhs, t.n_leaves, (p - 2) ** 2))).to(dev)
+    out = {}
+    for name, ti in (("full", False), ("shared", True)):
+        s = H.Solver(t, cd, p, q, translation_invariant=ti)
+        s.refactor(cd)
+        u = s.solve(fd, gd)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(reps):
+            s.refactor(cd)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        for _ in range(reps):
+            u = s.solve(fd, gd)
+        torch.cuda.synchronize()
+        f2 = time.perf_counter()
+        out[name] = {"factor_ms": (f1 - f0) * 1e3 / reps, "solve_ms_nrhs32": (f2 - f1) * 1e3 / reps,
+                     "operator_gb": t.workspace_bytes(p, q, translation_invariant=ti) / 1e9}
+        out[name + "_u"] = u
+        del s
+    us, uf = out.pop("shared_u"), out.pop("full_u")
+    out["rel_diff_shared_vs_full"] = float((us - uf).abs().max() / uf.abs().max())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +256,10 @@ def main():
     econ_diff = float((ue - u).abs().max() / u.abs().max())
     del se, ue
     ws_full, ws_econ = tree.workspace_bytes(P, Q), tree.workspace_bytes(P, Q, economic=True)
+    # translation-invariant builds, reported apart from the general path: the
+    # constant-coefficient heat operator on 128 x 128 leaves, p = 12, 32 RHS,
+    # full build vs one operator copy per distinct box
+    ti = translation_invariant_case(H, torch, dev, args.nrhs)
     # accuracy against stored oracle values (seed 2 = right-hand side 0)
     rel_err = rel_err_mixed = None
     ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
@@ -301,6 +342,7 @@ def main():
         "economic_rel_diff_vs_stored": econ_diff,
         "operator_gb_stored": ws_full / 1e9,
         "operator_gb_economic": ws_econ / 1e9,
+        "translation_invariant_heat_128x128_p12": ti,
         "rel_err_vs_oracle": rel_err,
         "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},

@@ -131,6 +131,7 @@ struct hps_handle {
   int econ_chunk = 0;
   // translation-invariant build: boxes with identical operators share one copy
   bool dedup = false;
+  hps::DevArray<int32_t> cflag;   // device flag of the constant-coefficient check
   std::vector<int64_t> off_T, off_X, off_S, off_LD, off_H;   // per box, -1 if absent
   int64_t scr_build = 0;          // scratch doubles the build needs
   // optional per-step timing (test hook): events around every launch step

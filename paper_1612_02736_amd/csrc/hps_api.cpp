@@ -1283,16 +1283,17 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
 
 extern "C" {
 
-// Host check that every leaf has the coefficients of leaf 0 (translation
-// invariant builds share operators between leaves).
-static int check_constant_coeffs(const double *coeffs, int nleaf, int p) {
-  const size_t per = size_t(6) * p * p;
-  std::vector<double> h(per * nleaf);
-  HIPCHK(hipMemcpy(h.data(), coeffs, h.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int i = 1; i < nleaf; ++i)
-    if (std::memcmp(&h[per * i], h.data(), per * sizeof(double)) != 0)
-      return fail(HPS_EINVAL, "translation_invariant: the coefficients of leaf " +
-                                  std::to_string(i) + " differ from leaf 0");
+// Device check that every leaf has the coefficients of leaf 0 (translation
+// invariant builds share operators between leaves); waits for the stream.
+static int check_constant_coeffs(hps_handle *H, const double *coeffs, hipStream_t st) {
+  if (!H->cflag.p) HIPCHK(H->cflag.alloc(1));
+  const int64_t per = int64_t(6) * H->p * H->p;
+  HIPCHK(hipMemsetAsync(H->cflag.p, 0, sizeof(int32_t), st));
+  HIPCHK(launch_block_diff(coeffs, per, per * H->nleaf, H->cflag.p, st));
+  int32_t f = 0;
+  HIPCHK(hipMemcpyAsync(&f, H->cflag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (f) return fail(HPS_EINVAL, "translation_invariant: the leaves' coefficients differ");
   return HPS_OK;
 }
 
@@ -1363,7 +1364,7 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
       return fail(HPS_EINVAL, "translation_invariant builds need a tree without refined interfaces");
   }
   if (H->dedup) {
-    rc = check_constant_coeffs(coeffs, H->nleaf, p);
+    rc = check_constant_coeffs(H.get(), coeffs, st);
     if (rc) return rc;
   }
   Layout Lo;
@@ -1446,7 +1447,7 @@ int hps_refactor(hps_handle *H, const double *coeffs, void *stream) {
   if (!H || !coeffs) return fail(HPS_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
   if (H->dedup) {
-    const int rc0 = check_constant_coeffs(coeffs, H->nleaf, H->p);
+    const int rc0 = check_constant_coeffs(H, coeffs, st);
     if (rc0) return rc0;
   }
   if (H->scr.n < size_t(H->scr_build)) HIPCHK(H->scr.alloc(H->scr_build));

@@ -1452,6 +1452,19 @@ __global__ __launch_bounds__(256) void cast_f32_kernel(const double *__restrict_
     dst[e] = float(src[e]);
 }
 
+// flag = 1 if any element differs from the same element of the first block
+// of `per` (translation-invariant builds: every leaf's coefficients equal
+// leaf 0's); NaN counts as different
+__global__ __launch_bounds__(256) void block_diff_kernel(const double *__restrict__ src,
+                                                         int64_t per, int64_t n,
+                                                         int32_t *__restrict__ flag) {
+  bool diff = false;
+  for (int64_t e = per + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * blockDim.x)
+    diff |= !(src[e] == src[e % per]);
+  if (diff) atomicOr(flag, 1);
+}
+
 __global__ __launch_bounds__(256) void fill_kernel(double *__restrict__ dst, double v, int64_t n) {
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
        e += int64_t(gridDim.x) * blockDim.x)
@@ -1674,6 +1687,14 @@ hipError_t launch_vecop(const VecOpDesc *descs, int nd, int64_t maxn, const Base
   if (nd <= 0) return hipSuccess;
   hipLaunchKernelGGL(vecop_kernel, dim3(grid_1d(maxn * nrhs, 64), nd), dim3(256), 0, st, descs,
                      nd, bs, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_diff(const double *src, int64_t per, int64_t n, int32_t *flag,
+                             hipStream_t st) {
+  if (n <= per) return hipSuccess;
+  hipLaunchKernelGGL(block_diff_kernel, dim3(grid_1d(n - per, 1024)), dim3(256), 0, st, src, per,
+                     n, flag);
   return hipGetLastError();
 }
 

@@ -45,6 +45,9 @@ hipError_t launch_copy_map(const Bases &bs, const VRef &dst, const VRef &src, in
 hipError_t launch_vecop(const VecOpDesc *descs, int nd, int64_t maxn, const Bases &bs, int nrhs,
                         hipStream_t st);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+// *flag |= 1 if src[e] != src[e % per] for some e < n (flag cleared by the caller)
+hipError_t launch_block_diff(const double *src, int64_t per, int64_t n, int32_t *flag,
+                             hipStream_t st);
 hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t st);
 
 }  // namespace hps
