@@ -788,6 +788,49 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_merge_kernel(
   if (tid == 0) info[d.info] = sh.info;
 }
 
+// Interface inversion X = (T33a - T33b)^-1 on the column-owner core (m up to
+// 64 RA and NW CB): same storage of X as gj_merge_kernel.
+template <int NW, int RA, int CB>
+__global__ __launch_bounds__(NW * 64) void gj2_merge_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, Bases bs,
+    int32_t *__restrict__ info) {
+  __shared__ GJ2Shared<NW, RA> sh;
+  const int idx = blockIdx.x;
+  if (idx >= nd) return;
+  const MergeInvDesc &d = descs[idx];
+  const double *Ta = (const double *)bs.d[BUF_WS] + d.Ta;
+  const double *Tb = (const double *)bs.d[BUF_WS] + d.Tb;
+  const int n = d.m;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double a[RA][CB];
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = lane + 64 * i;
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = wid + NW * b;
+      a[i][b] = (row < n && col < n)
+                    ? Ta[row + int64_t(col) * d.lda] - Tb[row + int64_t(col) * d.ldb]
+                    : 0.0;
+    }
+  }
+  gj2_core<NW, RA, CB>(a, n, lane, wid, sh);
+  double *X = (double *)bs.d[BUF_WS] + d.X;
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int row = lane + 64 * i;
+    if (row >= n) continue;
+    const int kr = sh.stepof[row];
+    const double sg = sh.sig[kr];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int col = wid + NW * b;
+      if (col < n) X[kr + int64_t(sh.pivrow[col]) * n] = sg * (a[i][b] + (col == kr ? 1.0 : 0.0));
+    }
+  }
+  if (tid == 0) info[d.info] = sh.info;
+}
+
 // ---------------------------------------------------------------------------
 // Blocked Gauss-Jordan for large interface blocks
 // ---------------------------------------------------------------------------
@@ -1541,16 +1584,16 @@ hipError_t launch_gj_merge(int cls, const MergeInvDesc *descs, int nd, const Bas
                          bs, info);
       break;
     case 1:
-      hipLaunchKernelGGL((gj_merge_kernel<8, 8, 8, 8>), dim3(nd), dim3(64), 0, st, descs, nd,
+      hipLaunchKernelGGL((gj2_merge_kernel<4, 1, 16>), dim3(nd), dim3(256), 0, st, descs, nd,
                          bs, info);
       break;
     case 2:
-      hipLaunchKernelGGL((gj_merge_kernel<16, 16, 8, 8>), dim3(nd), dim3(256), 0, st, descs,
-                         nd, bs, info);
+      hipLaunchKernelGGL((gj2_merge_kernel<8, 2, 16>), dim3(nd), dim3(512), 0, st, descs, nd,
+                         bs, info);
       break;
     case 3:
-      hipLaunchKernelGGL((gj_merge_kernel<28, 36, 7, 6>), dim3(nd), dim3(gj_threads<28, 36>()), 0, st,
-                         descs, nd, bs, info);
+      hipLaunchKernelGGL((gj2_merge_kernel<8, 4, 25>), dim3(nd), dim3(512), 0, st, descs, nd,
+                         bs, info);
       break;
     default:
       return hipErrorInvalidValue;
