@@ -185,3 +185,33 @@ class Perturbation:
 
     def __call__(self, x, y):
         return self.scale * self._raw(x, y)
+
+
+# -- accuracy experiments against an over-resolved self-reference ------------
+# Variable-coefficient Helmholtz (paper Sec. 7.2): -Lap u - kappa^2 (1 - c) u = g
+# on the unit square, c a sum of two Gaussians (the scattering potential), g a
+# Gaussian, kappa = 40; Dirichlet data 0 (the paper does not state it).
+HELM_KAPPA = 40.0
+
+
+def scattering_potential(x, y):
+    return (0.5 * np.exp(-200.0 * ((x - 0.35) ** 2 + (y - 0.6) ** 2))
+            + 0.5 * np.exp(-200.0 * ((x - 0.6) ** 2 + (y - 0.45) ** 2)))
+
+
+def helmholtz_coeffs(x, y, kappa=HELM_KAPPA):
+    z = np.zeros_like(x)
+    o = np.ones_like(x)
+    return np.stack([o, z, o.copy(), z, z.copy(),
+                     -kappa * kappa * (1.0 - scattering_potential(x, y))])
+
+
+def helmholtz_load(x, y):
+    return np.exp(-300.0 * ((x - 0.25) ** 2 + (y - 0.75) ** 2))
+
+
+# Poisson with an indicator load (paper Sec. 7.4): g = 1 on [1/4, 1/2]^2, else
+# 0, Dirichlet data 0 (not stated in the paper); the jumps lie on leaf edges
+# when the number of leaves per side is a multiple of 4.
+def indicator_load(x, y):
+    return ((x >= 0.25) & (x <= 0.5) & (y >= 0.25) & (y <= 0.5)).astype(float)
