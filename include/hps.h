@@ -85,9 +85,10 @@ typedef struct {
                             level, that have the same shape and position in
                             their parent get one shared copy of their
                             operators, built once.  hps_build and
-                            hps_refactor check the coefficients on the host
-                            and return HPS_EINVAL if they differ between
-                            leaves; not combined with economic. */
+                            hps_refactor compare the coefficients of every
+                            leaf with the first leaf's on the device and
+                            return HPS_EINVAL if any differ (bitwise); not
+                            combined with economic. */
 } hps_build_opts;
 
 enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
