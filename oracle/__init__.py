@@ -18,6 +18,7 @@ solver based on multidomain spectral discretization" (arXiv:1612.02736):
                    and 5.4 and the transposed (adjoint) sweeps.
 * ``dense``     -- an independent route: the global collocation system
                    assembled densely/sparsely and solved by a library LU.
+* ``timestep``  -- Crank-Nicolson steps with a fixed operator (Sec. 7.6).
 
 Everything is float64 with NumPy/SciPy (LAPACK getrf/getrs) primitives.
 """
@@ -28,10 +29,11 @@ from .tree import Tree
 from .leaf import leaf_operators, leaf_geometry
 from .hps import build, solve, solve_adjoint, coeff_gradient
 from .dense import dense_solve, assemble_system, residual
+from .timestep import operator_apply, crank_nicolson
 
 __all__ = [
     "cheb_nodes", "diff_matrix", "gauss_nodes", "interp_matrix", "bary_weights",
     "Tree", "leaf_operators", "leaf_geometry", "build", "solve",
     "solve_adjoint", "coeff_gradient", "dense_solve", "assemble_system",
-    "residual",
+    "residual", "operator_apply", "crank_nicolson",
 ]

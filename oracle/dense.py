@@ -12,7 +12,11 @@ u_c on every leaf and the value at every interior "master" Gauss node.  Rows:
   on refined, coarsened sides (Sec. 6.3);
 * E3 (flux continuity, Sec. 4): at a Gauss node shared by two leaves the two
   leaf fluxes D_ge,c u_c agree; at a coarse node of a refined interface the
-  coarse leaf's flux equals P_down applied to the fine leaves' fluxes.
+  coarse leaf's flux equals P_down applied to the fine leaves' fluxes;
+* side conditions (Sec. 7.6): a node on a Neumann side is an unknown whose
+  row sets its leaf's flux to the data; a node of a periodic seam is shared
+  by the leaves on the two sides and gets an ordinary E3 row.  Only
+  Dirichlet nodes are known values.
 
 ``dense_solve`` solves this system directly; ``residual`` evaluates b - K x.
 """
@@ -32,7 +36,7 @@ def _structure(tree, q):
     node_xy, bdry = tree.gauss(q)
     N = node_xy.shape[0]
     kind = np.zeros(N, dtype=int)            # 0 master, 1 boundary, 2 slave
-    kind[bdry] = 1
+    kind[bdry[tree.bdry_kind(q) == "D"]] = 1
     slave_rows = {}                          # slave -> [(coarse node, w)]
     coarse_fine = {}                         # coarse -> [(fine node, w)]
     for b in tree.boxes:
@@ -61,7 +65,10 @@ def assemble_system(tree, coeffs, p, q=None):
     p2 = p * p
     masters = np.where((kind == 0) & used)[0]
     mcol = {int(j): nl * p2 + k for k, j in enumerate(masters)}
-    bpos = {int(j): k for k, j in enumerate(bdry)}
+    bkind = tree.bdry_kind(q)
+    bpos = {int(j): k for k, j in enumerate(bdry) if bkind[k] == "D"}
+    npos = {int(j): k for k, j in enumerate(bdry) if bkind[k] == "N"}
+    e3_f = []                                # Neumann rows: (row, bdry index)
     nunk = nl * p2 + masters.size
     rows, cols, vals = [], [], []
     # right-hand-side maps: E1 rows take g; E2 rows take -(L f) terms
@@ -109,6 +116,9 @@ def assemble_system(tree, coeffs, p, q=None):
         own = owners[j]
         if len(own) == 2:
             terms = [(own[0], 1.0), (own[1], -1.0)]
+        elif j in npos:                     # Neumann: flux = data
+            terms = [(own[0], 1.0)]
+            e3_f.append((r, npos[j]))
         else:
             terms = [(own[0], 1.0)]
             for (fj, pw) in coarse_fine[j]:
@@ -123,8 +133,8 @@ def assemble_system(tree, coeffs, p, q=None):
     assert r == nunk, (r, nunk)
     K = sp.csr_matrix((vals, (rows, cols)), shape=(nunk, nunk))
     lay = dict(nl=nl, p2=p2, masters=masters, e1_rows=e1_rows, e2_f=e2_f,
-               nunk=nunk, kind=kind, slave_rows=slave_rows, bdry=bdry,
-               node_xy=node_xy)
+               e3_f=e3_f, nunk=nunk, kind=kind, slave_rows=slave_rows, bdry=bdry,
+               bkind=bkind, node_xy=node_xy)
     return K, lay
 
 
@@ -133,6 +143,8 @@ def _rhs(lay, f, g):
     b[lay["e1_rows"].ravel()] = np.asarray(g).ravel()
     for (r, k, wgt) in lay["e2_f"]:
         b[r] += wgt * f[k]
+    for (r, k) in lay["e3_f"]:
+        b[r] += f[k]
     return b
 
 
@@ -142,7 +154,8 @@ def _unpack(lay, x, f):
     N = lay["kind"].size
     u = np.zeros(N)
     u[lay["masters"]] = x[nl * p2:]
-    u[lay["bdry"]] = f
+    dm = lay["bkind"] == "D"
+    u[lay["bdry"][dm]] = np.asarray(f)[dm]
     for j, terms in lay["slave_rows"].items():
         u[j] = sum(w * u[c] for (c, w) in terms)
     return u_c, u

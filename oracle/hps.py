@@ -10,6 +10,13 @@
   on coarsened boxes, Sec. 6.4); downward pass u(root boundary) = f,
   u_gi = S u_ge + w at parents (u_ge,fine = P_up u_ge first, Sec. 6.4),
   u_c = S u_ge + F g at leaves.
+* Neumann sides (Sec. 7.6 states that the algorithm is unchanged; the
+  closure is our reading): the root's own relation flux = T u + h holds on
+  its boundary, so on the Neumann nodes N, with the Dirichlet nodes D known,
+  T_NN u_N = psi - h_N - T_ND f_D.  This is the merge formula of Sec. 4 with
+  the outside as a sibling whose T is zero and whose flux is the data psi.
+  Periodic sides need nothing here: the tree identifies their nodes and the
+  ordinary merges eliminate them.
 * ``solve_adjoint`` -- the transpose of the linear map (f, g) -> u_c of
   Algorithm 2, taken step by step in reverse order (not in the paper).
 * ``coeff_gradient`` -- dL/dc for the nodal coefficients: with lambda the
@@ -54,6 +61,13 @@ def build(tree, coeffs, p, q=None):
     """Algorithm 1.  coeffs: [n_leaves, 6, p*p] in canonical leaf order."""
     if q is None:
         q = p - 1
+    for P in tree.problems:
+        if "D" not in P["bc"] and q > p - 2:
+            # with q = p - 1 the Gauss -> Chebyshev map of every leaf has a
+            # null vector (phi on horizontal edges, -phi on vertical edges,
+            # phi vanishing at an edge's p - 2 inner Chebyshev nodes); only
+            # Dirichlet data removes it, so the global system is singular
+            raise ValueError("a problem without a Dirichlet side needs q <= p - 2")
     tree.gauss(q)
     leaves = tree.leaves
     leaf_pos = {b.id: i for i, b in enumerate(leaves)}
@@ -84,18 +98,37 @@ def build(tree, coeffs, p, q=None):
             o["T"] = T
         ops.box[tau.id] = o
     ops.leaf_pos = leaf_pos
+    # Neumann closure of each root: LU of T_NN and the block T_ND
+    _, bdry = tree.gauss(q)
+    kind = tree.bdry_kind(q)
+    neu = set(int(j) for j in bdry[kind == "N"])
+    ops.closure = {}
+    for r in tree.roots:
+        iN = [i for i, j in enumerate(r.ge) if j in neu]
+        if not iN:
+            continue
+        iD = [i for i, j in enumerate(r.ge) if j not in neu]
+        T = ops.box[r.id]["T"]
+        lu = sla.lu_factor(T[np.ix_(iN, iN)])
+        if np.any(np.diag(lu[0]) == 0.0):
+            raise np.linalg.LinAlgError("singular Neumann closure")
+        ops.closure[r.id] = dict(iN=np.array(iN, int), iD=np.array(iD, int), lu=lu,
+                                 TND=T[np.ix_(iN, iD)])
     return ops
 
 
 def solve(ops, f, g):
     """Algorithm 2 for one right-hand side.
 
-    f: [n_bdry] Dirichlet data at the canonical boundary Gauss nodes;
+    f: [n_bdry] boundary data at the canonical boundary Gauss nodes (u on
+    Dirichlet sides, the flux on Neumann sides, ignored on periodic sides);
     g: [n_leaves, (p-2)^2] body load at leaf interior Chebyshev nodes.
     Returns (u_c [n_leaves, p*p], u [N] at every Gauss node).
     """
     tree, p, q = ops.tree, ops.p, ops.q
     node_xy, bdry = tree.gauss(q)
+    kind = tree.bdry_kind(q)
+    f = np.asarray(f, dtype=float)
     boxes = tree.boxes
     h = {}
     w = {}
@@ -110,7 +143,17 @@ def solve(ops, f, g):
         hf = np.concatenate([ha[p1a], hb[p2b]]) + o["Q"] @ w[tau.id]
         h[tau.id] = tau.Pdown @ hf if tau.Pdown is not None else hf
     u = np.zeros(node_xy.shape[0])
-    u[bdry] = f
+    u[bdry[kind == "D"]] = f[kind == "D"]
+    if ops.closure:
+        neu_pos = {int(bdry[i]): i for i in np.where(kind == "N")[0]}
+        for r in tree.roots:
+            c = ops.closure.get(r.id)
+            if c is None:
+                continue
+            ge = np.array(r.ge)
+            psi = np.array([f[neu_pos[int(j)]] for j in ge[c["iN"]]])
+            rhs = psi - h[r.id][c["iN"]] - c["TND"] @ u[ge[c["iD"]]]
+            u[ge[c["iN"]]] = sla.lu_solve(c["lu"], rhs)
     u_c = np.zeros((len(tree.leaves), p * p))
     for tau in boxes:                                # downward pass
         o = ops.box[tau.id]
@@ -128,9 +171,12 @@ def solve(ops, f, g):
 def solve_adjoint(ops, ubar_c):
     """Transpose of (f, g) -> u_c.  ubar_c: [n_leaves, p*p].
 
-    Returns (fbar [n_bdry], gbar [n_leaves, (p-2)^2]).
+    Returns (fbar [n_bdry], gbar [n_leaves, (p-2)^2]).  Dirichlet problems
+    only.
     """
     tree, p, q = ops.tree, ops.p, ops.q
+    if any(P["bc"] != ("D", "D", "D", "D") for P in tree.problems):
+        raise NotImplementedError("the adjoint covers Dirichlet problems")
     node_xy, bdry = tree.gauss(q)
     boxes = tree.boxes
     N = node_xy.shape[0]

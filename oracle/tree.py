@@ -25,6 +25,18 @@ Readings where the paper is silent:
   panel containing it (the average of two panels on an exact junction).  With
   two equal panels this is the paper's pair of q -> q/2 blocks.
 
+* Side conditions (Sec. 7.6 uses zero Neumann data on two sides and
+  periodicity on the other two, and states that the algorithm is unchanged):
+  each side of a problem is Dirichlet ('D'), Neumann ('N') or periodic ('P',
+  in opposite pairs).  A periodic pair is one set of Gauss nodes: the east
+  (north) side's segments are the west (south) side's, so the seam is an
+  interface like any other and the merge whose children meet across it
+  eliminates it.  On Neumann sides the data is the boundary flux in the
+  convention of Sec. 3.1 (+d/dx on vertical sides, +d/dy on horizontal
+  sides); the nodes stay unknowns of the root.  The canonical boundary list
+  keeps all four sides; entries of a periodic side name the seam nodes and
+  carry no data.
+
 Geometry is kept in integers: one base leaf spans ``U`` units per direction,
 so every refined box, edge and junction is exact.
 """
@@ -72,7 +84,8 @@ class Tree:
         t = cls(tie)
         for _ in range(n_problems):
             t.problems.append(dict(X0=float(x0), X1=float(x1), Y0=float(y0),
-                                   Y1=float(y1), nx=int(nx), ny=int(ny)))
+                                   Y1=float(y1), nx=int(nx), ny=int(ny),
+                                   bc=("D", "D", "D", "D")))
             t.quad_leaves.append({(i * U, j * U, U, U, 0)
                                   for i in range(nx) for j in range(ny)})
         return t
@@ -82,6 +95,18 @@ class Tree:
         x = P["X0"] + (P["X1"] - P["X0"]) * (ix / (P["nx"] * U))
         y = P["Y0"] + (P["Y1"] - P["Y0"]) * (iy / (P["ny"] * U))
         return x, y
+
+    def set_bc(self, bc, problem=None):
+        """Side conditions (S, E, N, W), each 'D', 'N' or 'P'; periodic
+        sides come in opposite pairs.  problem=None: every problem."""
+        bc = tuple(bc)
+        if len(bc) != 4 or any(k not in ("D", "N", "P") for k in bc):
+            raise ValueError("bc must be four of 'D', 'N', 'P'")
+        if (bc[1] == "P") != (bc[3] == "P") or (bc[0] == "P") != (bc[2] == "P"):
+            raise ValueError("periodic sides come in opposite pairs")
+        for k in (range(len(self.problems)) if problem is None else [problem]):
+            self.problems[k]["bc"] = bc
+        self._boxes = None
 
     def refine_point(self, problem, px, py, n_ref, t=np.sqrt(2.0)):
         """Sec. 6.1: n_ref rounds of splitting every close leaf into 2x2."""
@@ -190,8 +215,24 @@ class Tree:
         g = gauss_nodes(q)
         seg_id = {}
         segs = []
+        for p, P in enumerate(self.problems):
+            bc = P["bc"]
+            if bc[1] == "P" and P["nx"] < 2 or bc[0] == "P" and P["ny"] < 2:
+                raise ValueError("a periodic direction needs at least two leaves")
+            for (ix, iy, w, h, d) in self.quad_leaves[p]:
+                if d > 0 and (bc[1] == "P" and (ix == 0 or ix + w == P["nx"] * U) or
+                              bc[0] == "P" and (iy == 0 or iy + h == P["ny"] * U)):
+                    raise ValueError("refined leaves on a periodic side")
 
         def seg(key):
+            # a periodic pair is one set of nodes: east onto west, north onto
+            # south
+            p, o, fx = key[0], key[1], key[2]
+            P = self.problems[p]
+            if o == "v" and P["bc"][1] == "P" and fx == P["nx"] * U:
+                key = (p, o, 0) + key[3:]
+            if o == "h" and P["bc"][0] == "P" and fx == P["ny"] * U:
+                key = (p, o, 0) + key[3:]
             if key not in seg_id:
                 seg_id[key] = len(segs)
                 segs.append(key)
@@ -242,21 +283,31 @@ class Tree:
             if b.kind == "quad" or (b.kind == "base" and b.ix1 - b.ix0 == U
                                     and b.iy1 - b.iy0 == U):
                 self._coarsen(b, q, g, quad_set[b.problem], nodes_of)
-        # canonical boundary nodes of each problem: S, E, N, W
-        bd = []
+        # canonical boundary nodes of each problem: S, E, N, W (a periodic
+        # side lists the seam nodes it shares with its partner)
+        bd, kinds = [], []
         for p, P in enumerate(self.problems):
             W, H = P["nx"] * U, P["ny"] * U
-            sides = [("h", 0), ("v", W), ("h", H), ("v", 0)]
-            for (o, fx) in sides:
+            bc = P["bc"]
+            sides = [("h", 0), ("v", 0 if bc[1] == "P" else W),
+                     ("h", 0 if bc[2] == "P" else H), ("v", 0)]
+            for side, (o, fx) in enumerate(sides):
                 ss = [s for s, k in enumerate(segs)
                       if k[0] == p and k[1] == o and k[2] == fx]
                 ss.sort(key=lambda s: segs[s][3])
                 for s in ss:
                     bd += nodes_of(s)
+                    kinds += [bc[side]] * q
         self._node_xy = xy
         self._bdry = np.array(bd, dtype=np.int64)
+        self._bdry_kind = np.array(kinds)
         self._q = q
         return xy, self._bdry
+
+    def bdry_kind(self, q):
+        """'D', 'N' or 'P' for every canonical boundary entry."""
+        self.gauss(q)
+        return self._bdry_kind
 
     def _coarsen(self, b, q, g, quads, nodes_of):
         """Sec. 6.3: replace fine nodes on each side that faces an unrefined

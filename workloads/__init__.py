@@ -215,3 +215,64 @@ def helmholtz_load(x, y):
 # when the number of leaves per side is a multiple of 4.
 def indicator_load(x, y):
     return ((x >= 0.25) & (x <= 0.5) & (y >= 0.25) & (y <= 0.5)).astype(float)
+
+
+# -- workload 7: Crank-Nicolson step of convection-diffusion (Sec. 7.6) -------
+# u_t = eps Lap u - u_x on [0,1]^2, periodic in x, zero Neumann data in y,
+# initial value exp(-alpha |x - xhat|^2).  One step with time step k solves
+# (I/k - A/2) u_new = (I/k + A/2) u_old with A = eps Lap - d/dx; in the form
+# of the problem statement the left operator has c11 = c22 = eps/2, c1 = 1/2,
+# c = 1/k.
+CD_EPS = 1.0 / 200.0
+CD_ALPHA = 50.0
+CD_XHAT = (0.25, 0.25)
+
+
+def convdiff_coeffs(x, y, k, eps=CD_EPS):
+    z = np.zeros_like(x)
+    e = np.full_like(x, 0.5 * eps)
+    return np.stack([e, z, e.copy(), np.full_like(x, 0.5), z.copy(), np.full_like(x, 1.0 / k)])
+
+
+def convdiff_initial(x, y, alpha=CD_ALPHA, xhat=CD_XHAT):
+    return np.exp(-alpha * ((x - xhat[0]) ** 2 + (y - xhat[1]) ** 2))
+
+
+class PolyYSolution:
+    """u = sum_{j <= deg} a_j y^j with a ~ N(0,1) (seeded): constant in x, so
+    periodic in x for any period."""
+
+    def __init__(self, seed, deg):
+        self.a = np.random.default_rng(seed).standard_normal(deg + 1)
+
+    def derivs(self, x, y):
+        z = np.zeros_like(x)
+        u, uy, uyy = z.copy(), z.copy(), z.copy()
+        for j, a in enumerate(self.a):
+            u += a * y ** j
+            if j >= 1:
+                uy += a * j * y ** (j - 1)
+            if j >= 2:
+                uyy += a * j * (j - 1) * y ** (j - 2)
+        return u, z.copy(), uy, z.copy(), z.copy(), uyy
+
+    def u(self, x, y):
+        return self.derivs(x, y)[0]
+
+    def g(self, x, y, coeffs):
+        return apply_A(coeffs, *self.derivs(x, y))
+
+
+def side_data(sol, xy, kinds, rect):
+    """Boundary data at boundary nodes xy [n, 2] with side conditions kinds
+    ('D', 'N' or 'P' per node) on the rectangle (X0, X1, Y0, Y1): u on
+    Dirichlet sides, the flux +u_x (vertical sides) or +u_y (horizontal
+    sides) on Neumann sides, 0 on periodic sides."""
+    x, y = xy[:, 0], xy[:, 1]
+    u, ux, uy = sol.derivs(x, y)[:3]
+    X0, X1, Y0, Y1 = rect
+    tol = 1e-12 * max(X1 - X0, Y1 - Y0)
+    horiz = (np.abs(y - Y0) <= tol) | (np.abs(y - Y1) <= tol)
+    flux = np.where(horiz, uy, ux)
+    kinds = np.asarray(kinds)
+    return np.where(kinds == "D", u, np.where(kinds == "N", flux, 0.0))
