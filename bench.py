@@ -151,6 +151,45 @@ def translation_invariant_case(H, torch, dev, nrhs, reps=3):
     return out
 
 
+def crank_nicolson_case(H, torch, dev, k=0.01, steps=50):
+    """The parabolic problem of Sec. 7.6: u_t = eps Lap u - u_x on 16 x 16
+    leaves, periodic in x, zero Neumann data in y, Crank-Nicolson with time
+    step k (p = 16, q = 14).  One step = the right side sigma u - L u on the
+    leaf grids plus one solve.  The initial value is the eigenmode
+    e^{2 pi i x} cos(pi y), whose Crank-Nicolson iterates are known in closed
+    form, so the error of the run is reported too."""
+    import workloads as W
+    n, p, q = 16, 16, 14
+    t = H.Tree(0.0, 1.0, 0.0, 1.0, n, n).set_bc("NPNP")
+    xy = t.leaf_cheb_nodes(p)
+    X, Y = xy[..., 0], xy[..., 1]
+    coeffs = np.stack([W.convdiff_coeffs(X[i], Y[i], k) for i in range(t.n_leaves)])
+    cd = torch.from_numpy(coeffs).to(dev)
+    s = H.Solver(t, cd, p, q)
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
+    s.refactor(cd)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - b0) * 1e3
+    f = torch.zeros((1, s.n_bdry), dtype=torch.float64, device=dev)
+    u0 = torch.from_numpy((np.cos(2 * np.pi * X) * np.cos(np.pi * Y))[None]).to(dev)
+    u = s.solve(f, s.apply_operator(u0, 2.0 / k))     # warm-up step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = u0
+    for _ in range(steps):
+        u = s.solve(f, s.apply_operator(u, 2.0 / k))
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / steps
+    lam = 5 * W.CD_EPS * np.pi ** 2 + 2j * np.pi
+    R = (1 - k * lam / 2) / (1 + k * lam / 2)
+    closed = np.real(R ** steps * np.exp(2j * np.pi * X)) * np.cos(np.pi * Y)
+    err = float(np.abs(u[0].cpu().numpy() - closed).max() / np.abs(closed).max())
+    return {"leaves": n * n, "p": p, "q": q, "k": k, "steps": steps, "build_ms": build_ms,
+            "step_ms": step_ms, "steps_per_s": 1e3 / step_ms,
+            "rel_err_vs_cn_closed_form": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +300,7 @@ def main():
     # constant-coefficient heat operator on 128 x 128 leaves, p = 12, 32 RHS,
     # full build vs one operator copy per distinct box
     ti = translation_invariant_case(H, torch, dev, args.nrhs)
+    cn = crank_nicolson_case(H, torch, dev)
     # accuracy against stored oracle values (seed 2 = right-hand side 0)
     rel_err = rel_err_mixed = None
     ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
@@ -343,6 +383,7 @@ def main():
         "operator_gb_stored": ws_full / 1e9,
         "operator_gb_economic": ws_econ / 1e9,
         "translation_invariant_heat_128x128_p12": ti,
+        "crank_nicolson_periodic_neumann_16x16_p16": cn,
         "rel_err_vs_oracle": rel_err,
         "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},

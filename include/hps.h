@@ -117,6 +117,28 @@ typedef struct {
 int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
                      int ny, int n_problems, hps_tree **out);
 
+/* Side conditions (Sec. 7.6 solves a problem with zero Neumann data on two
+ * sides and periodicity on the other two).  bc[4] gives sides S, E, N, W of
+ * problem `problem` (-1: every problem):
+ *  - HPS_BC_DIRICHLET: u is given (the default);
+ *  - HPS_BC_NEUMANN: the flux is given, in the convention above (+d/dx on
+ *    vertical sides, +d/dy on horizontal sides; the outward normal derivative
+ *    is minus the data on the S and W sides);
+ *  - HPS_BC_PERIODIC: opposite sides are identified (both of a pair).
+ * A periodic pair shares one set of Gauss nodes, and the merge whose two
+ * children meet across the seam eliminates it.  Neumann nodes stay exterior
+ * up to the root, and one more elimination above the root solves the root's
+ * relation flux = T u + h on them (the merge of Sec. 4 with a sibling whose
+ * T is zero and whose flux is the data).  Build-time rules: a periodic
+ * direction needs at least 4 leaves and no refined leaf on its sides; a
+ * problem with a Neumann side needs at least 2 leaves; a problem without a
+ * Dirichlet side needs q <= p - 2 (with q = p - 1 its discrete system is
+ * singular).  Handles of trees with a non-Dirichlet side solve in FP64 or
+ * FP32 only (no HPS_PREC_MIXED, no adjoint, no translation_invariant).
+ * Errors: HPS_EINVAL (unknown code, unpaired periodic side, bad problem). */
+enum { HPS_BC_DIRICHLET = 0, HPS_BC_NEUMANN = 1, HPS_BC_PERIODIC = 2 };
+int hps_tree_set_bc(hps_tree *tree, int problem, const int *bc);
+
 /* Sec. 6.1: n_ref rounds of splitting into 2 x 2 every leaf of problem
  * `problem` whose distance to (px, py) is <= t * (half its side); t = sqrt(2)
  * in the paper.  Must be called before hps_build; invalidates earlier
@@ -137,7 +159,8 @@ int hps_leaf_cheb_nodes(const hps_tree *tree, int p, double *xy);
 /* host out [n_leaves][4]: x0, x1, y0, y1 of every leaf. */
 int hps_leaf_boxes(const hps_tree *tree, double *boxes);
 
-/* host out [n_bdry][2]: canonical boundary Gauss nodes. */
+/* host out [n_bdry][2]: canonical boundary Gauss nodes (on a periodic side,
+ * the seam nodes it shares with its partner, at the partner's coordinates). */
 int hps_bdry_gauss_nodes(const hps_tree *tree, int q, double *xy);
 
 /* host out [n_gauss][2]: every Gauss node in the order of u_gauss. */
@@ -176,7 +199,8 @@ size_t hps_build_workspace_size_opts(const hps_tree *tree, int p, int q, int eco
 
 /* -- solve stage (Algorithm 2) -------------------------------------------- */
 
-/* f: device [nrhs][n_bdry] (canonical boundary order);
+/* f: device [nrhs][n_bdry] (canonical boundary order): u on Dirichlet
+ *    sides, the flux on Neumann sides, ignored on periodic sides;
  * g: device [nrhs][n_leaves][(p-2)^2] (interior Chebyshev nodes);
  * u: device out [nrhs][n_leaves][p*p].
  * Upward pass h = H g, w = X(h3b - h3a), h = [h1a; h2b] + [T13a; T23b] w;
@@ -200,6 +224,15 @@ int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs,
  * nodes (only the collocated PDE rows depend on c). */
 int hps_coeff_grad_c(hps_handle *h, const double *u, const double *gbar,
                      int nrhs, double *cbar, void *stream);
+
+/* sigma u - A u at the interior Chebyshev nodes of every leaf, with A the
+ * handle's collocated operator (Sec. 3.2, the coefficients of the last build
+ * or refactor).  u: device [nrhs][n_leaves][p*p]; out: device
+ * [nrhs][n_leaves][(p-2)^2].  An implicit step u_t = A' u with the handle
+ * built for L = I/k - A'/2 (Crank-Nicolson, Sec. 7.6) takes the right side
+ * (I/k + A'/2) u = (2/k) u - L u, i.e. sigma = 2/k. */
+int hps_apply_operator(hps_handle *h, const double *u, int nrhs, double sigma, double *out,
+                       void *stream);
 
 void hps_handle_free(hps_handle *h);
 

@@ -89,6 +89,13 @@ int hps_tree_refine_point(hps_tree *tree, int problem, double px, double py, int
   return HPS_OK;
 }
 
+int hps_tree_set_bc(hps_tree *tree, int problem, const int *bc) {
+  if (!tree || !bc) return fail(HPS_EINVAL, "NULL argument");
+  std::string e = set_bc(tree->t, problem, bc);
+  if (!e.empty()) return fail(HPS_EINVAL, e);
+  return HPS_OK;
+}
+
 static int plan_tree(const TreeDesc &t, Plan &pl, int q) {
   std::string e = build_tree_boxes(t, pl);
   if (!e.empty()) return fail(HPS_ETREE, e);
@@ -195,6 +202,7 @@ struct Layout {
   std::vector<int64_t> h, w, hn;                          // vec offsets
   std::vector<int64_t> Ub, Ubn, wb, hb, hbn;              // adjoint vec offsets
   std::vector<int64_t> map_fin, map_nat, map_gi, map_pi, map_slave;  // imap offsets
+  std::vector<int64_t> Z0, map_psi;   // Neumann closure: zero sibling T (ws), data positions
   std::vector<int64_t> L_role;                 // ws, per role (5)
   std::vector<int64_t> Dci, T0;                // ws, per (class*5 + role)
   int64_t ws = 0, scr = 0, vec = 0, imap = 0, ipiv_n = 0, solve_ws = 0;
@@ -366,6 +374,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   // identical operators, stored once at the key's first box (rep).
   std::vector<int> rep(nb);
   for (int b = 0; b < nb; ++b) rep[b] = b;
+  if (H->dedup && pl.general_bc)
+    return fail(HPS_EINVAL, "translation_invariant builds need Dirichlet sides");
   if (H->dedup) {
     std::map<std::vector<int64_t>, int> first;
     std::vector<int64_t> kid(nb, -1);
@@ -434,6 +444,14 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     ws_blocks.push_back({Lo.L_role[r], L});
   }
   Lo.solve_ws = Lo.ws;
+  // Neumann closure boxes merge with a sibling whose T is zero
+  Lo.Z0.assign(nb, -1);
+  for (int b = 0; b < nb; ++b)
+    if (pl.boxes[b].kind == 3) {
+      const int64_t m = (int64_t)pl.boxes[b].gi.size();
+      Lo.Z0[b] = ws_take(m * m);
+      ws_blocks.push_back({Lo.Z0[b], std::vector<double>(size_t(m * m), 0.0)});
+    }
   const int ncls = (int)pl.size_class.size();
   Lo.Dci.assign(size_t(ncls) * 5, -1);
   Lo.T0.assign(size_t(ncls) * 5, -1);
@@ -551,6 +569,22 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     H->ici_map = imap_put(w);
     H->map_bdry = imap_put64(pl.bdry);
     H->n_bdry = (int64_t)pl.bdry.size();
+    // position of each Neumann node's data in the boundary vector
+    std::unordered_map<int64_t, int32_t> npos;
+    for (size_t k = 0; k < pl.bdry.size(); ++k)
+      if (pl.bdry_kind[k] == kBcNeumann) npos[pl.bdry[k]] = (int32_t)k;
+    Lo.map_psi.assign(nb, -1);
+    for (int b = 0; b < nb; ++b) {
+      const Box &B = pl.boxes[b];
+      if (B.kind != 3) continue;
+      std::vector<int32_t> v;
+      for (int64_t j : B.gi) {
+        auto it = npos.find(j);
+        if (it == npos.end()) return fail(HPS_ETREE, "closure node without Neumann data");
+        v.push_back(it->second);
+      }
+      Lo.map_psi[b] = imap_put(v);
+    }
   }
   // aux: Dh, Dh2
   ws_init.clear();
@@ -646,14 +680,22 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     std::vector<MergeInvDesc> levd;
     for (int b : lev) {
       const Box &B = pl.boxes[b];
-      const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+      const Box &A = pl.boxes[B.alpha];
       const int m = (int)B.gi.size();
-      const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
-      const int n1 = ea - m, n2 = eb - m;
+      const int ea = (int)A.fin.size();
+      const int n1 = ea - m;
       MergeInvDesc d{};
       d.Ta = Lo.T[B.alpha] + n1 + int64_t(n1) * ea;
-      d.Tb = Lo.T[B.beta] + n2 + int64_t(n2) * eb;
-      d.lda = ea; d.ldb = eb; d.m = m; d.info = info_slot++;
+      d.lda = ea; d.m = m; d.info = info_slot++;
+      if (B.kind == 3) {               // closure: the sibling's T is zero
+        d.Tb = Lo.Z0[b];
+        d.ldb = m;
+      } else {
+        const Box &C = pl.boxes[B.beta];
+        const int eb = (int)C.fin.size(), n2 = eb - m;
+        d.Tb = Lo.T[B.beta] + n2 + int64_t(n2) * eb;
+        d.ldb = eb;
+      }
       d.X = Lo.X[b];
       d.W = Lo.W_scr[b];
       d.ipiv = Lo.ipiv[b];
@@ -664,16 +706,20 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     GemmList sg, tg, c1, c2;
     for (int b : lev) {
       const Box &B = pl.boxes[b];
-      const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+      const Box &A = pl.boxes[B.alpha];
       const int m = (int)B.gi.size();
-      const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
-      const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
+      const int ea = (int)A.fin.size();
+      const int n1 = ea - m;
       GemmDesc g{};
       g.M = m; g.N = n1; g.K = m;
       g.A = ref(BUF_WS, Lo.X[b], m); g.B = ref(BUF_WS, Lo.T[B.alpha] + n1, ea);
       g.C = ref(BUF_WS, Lo.S[b], m); g.D = noref(); g.crow = g.ccol = -1;
       g.alpha = -1.0; g.beta = 0.0;
-      sg.add(g);
+      if (n1 > 0) sg.add(g);
+      if (B.kind == 3) continue;      // closure: S = -X T31a only, no T above
+      const Box &C = pl.boxes[B.beta];
+      const int eb = (int)C.fin.size();
+      const int n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
       g = GemmDesc{};
       g.M = m; g.N = n2; g.K = m;
       g.A = ref(BUF_WS, Lo.X[b], m); g.B = ref(BUF_WS, Lo.T[B.beta] + n2, eb);
@@ -781,6 +827,21 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     a.alpha = 1.0; a.beta = 0.0;
     return a;
   };
+  auto vecop_step = [&](std::vector<VecOpDesc> &tmp, std::vector<Step> &prg) {
+    if (tmp.empty()) return;
+    Step s{S_VECOP};
+    s.d0 = (int64_t)vops.size();
+    s.nd = (int64_t)tmp.size();
+    for (auto &v : tmp) s.maxm = std::max(s.maxm, v.n);
+    vops.insert(vops.end(), tmp.begin(), tmp.end());
+    prg.push_back(s);
+    tmp.clear();
+  };
+  auto vop = [&](int n, VRef dst, VRef a, double ca, VRef b, double cb) {
+    VecOpDesc v{};
+    v.n = n; v.dst = dst; v.a = a; v.b = b; v.ca = ca; v.cb = cb;
+    return v;
+  };
   // up pass
   {
     auto &up = H->up_prog;
@@ -802,8 +863,19 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       std::vector<ApplyDesc> wst, hst, cst;
       for (int b : lev) {
         const Box &B = pl.boxes[b];
-        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+        const Box &A = pl.boxes[B.alpha];
         const int m = (int)B.gi.size();
+        if (B.kind == 3) {
+          // Neumann closure: w = X (psi - h3a), psi read from the boundary data
+          const int n1 = (int)A.fin.size() - m;
+          ApplyDesc a = ad(m, m, 0, 1, Lo.X[b], m);
+          a.B1 = vref(BUF_IN0, 0, Lo.map_psi[b], H->n_bdry);
+          a.B2 = vref(BUF_VEC, Lo.h[B.alpha] + n1, -1, kInterleaved);
+          a.C = vref(BUF_VEC, Lo.w[b], -1, kInterleaved);
+          wst.push_back(a);
+          continue;
+        }
+        const Box &C = pl.boxes[B.beta];
         const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
         const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
         ApplyDesc a = ad(m, m, 0, 1, Lo.X[b], m);
@@ -850,9 +922,17 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         if (!pl.boxes[b].leaf && pl.boxes[b].height == h) lev.push_back(b);
       if (lev.empty()) continue;
       std::vector<ApplyDesc> sl, ug;
+      std::vector<VecOpDesc> cp;
       for (int b : lev) {
         const Box &B = pl.boxes[b];
         const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
+        if (en == 0) {                 // a closure with no Dirichlet side: u_gi = w
+          VecOpDesc v = vop(m, vref(BUF_VEC, H->ug_off, Lo.map_gi[b], kInterleaved),
+                            vref(BUF_VEC, Lo.w[b], -1, kInterleaved), 1.0, vref(-1, 0, -1, 0), 0.0);
+          v.b.buf = -1;
+          cp.push_back(v);
+          continue;
+        }
         if (B.coarsened && !B.slave_rows.empty()) {
           ApplyDesc a = ad((int)B.slave_rows.size(), ef, 0, 0, Lo.Pups[b], (int)B.slave_rows.size());
           a.B1 = vref(BUF_VEC, H->ug_off, Lo.map_fin[b], kInterleaved);
@@ -868,6 +948,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       }
       apply_step(sl, dn);
       apply_step(ug, dn);
+      vecop_step(cp, dn);
     }
     for (int i = 0; i < nleaf; ++i) {
       const int li = pl.leaves[i];
@@ -919,21 +1000,6 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     apply_step(tmp, prg);
     prg.back().trans = true;
   };
-  auto vecop_step = [&](std::vector<VecOpDesc> &tmp, std::vector<Step> &prg) {
-    if (tmp.empty()) return;
-    Step s{S_VECOP};
-    s.d0 = (int64_t)vops.size();
-    s.nd = (int64_t)tmp.size();
-    for (auto &v : tmp) s.maxm = std::max(s.maxm, v.n);
-    vops.insert(vops.end(), tmp.begin(), tmp.end());
-    prg.push_back(s);
-    tmp.clear();
-  };
-  auto vop = [&](int n, VRef dst, VRef a, double ca, VRef b, double cb) {
-    VecOpDesc v{};
-    v.n = n; v.dst = dst; v.a = a; v.b = b; v.ca = ca; v.cb = cb;
-    return v;
-  };
   // solve with a flux-jump source: the up pass with the B3 operand enabled
   {
     H->up_jump_prog.clear();
@@ -961,8 +1027,11 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     apply_step(tmp, H->ext_prog);
   }
   // adjoint, reverse of the downward pass (children before parents):
-  // inputs ubar (BUF_IN0), outputs fbar (BUF_IN1) and gbar (BUF_IN2)
-  {
+  // inputs ubar (BUF_IN0), outputs fbar (BUF_IN1) and gbar (BUF_IN2);
+  // Dirichlet problems only (no closure boxes, no periodic seams)
+  H->adj_down_prog.clear();
+  H->adj_up_prog.clear();
+  if (!pl.general_bc) {
     auto &P = H->adj_down_prog;
     P.clear();
     std::vector<ApplyDesc> t1, t2;
@@ -1044,7 +1113,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     vecop_step(fv, P);
   }
   // adjoint, reverse of the upward pass (parents before children)
-  {
+  if (!pl.general_bc) {
     auto &P = H->adj_up_prog;
     P.clear();
     for (int h = pl.max_height; h >= 1; --h) {
@@ -1355,8 +1424,18 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
     return fail(HPS_EINVAL, "economic and translation_invariant builds do not combine");
   int rc = plan_tree(H->tree, H->pl, q);
   if (rc) return rc;
+  if (H->dedup && H->pl.general_bc)
+    return fail(HPS_EINVAL, "translation_invariant builds need Dirichlet sides");
   H->p = p; H->q = q; H->mi = (p - 2) * (p - 2); H->me = 4 * (p - 1); H->g4 = 4 * q;
   H->nleaf = (int)H->pl.leaves.size();
+  for (const Problem &P : H->tree.probs) {
+    bool dirichlet = false;
+    for (int s = 0; s < 4; ++s) dirichlet |= P.bc[s] == kBcDirichlet;
+    // with q = p - 1 the leaf Gauss -> Chebyshev maps share a null vector
+    // that only Dirichlet data removes
+    if (!dirichlet && q > p - 2)
+      return fail(HPS_EINVAL, "a problem without a Dirichlet side needs q <= p - 2");
+  }
   for (const Box &b : H->pl.boxes) {
     if (!b.leaf && (int)b.gi.size() > 2048)
       return fail(HPS_EINVAL, "interface longer than 2048 nodes");

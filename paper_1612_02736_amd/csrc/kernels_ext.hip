@@ -15,12 +15,14 @@ namespace hps {
 // coefficients and reference matrices are read once).  Residual of the
 // collocated PDE at interior nodes, r = g - A u (Sec. 3.2, same A as the
 // build), and the leaf's boundary fluxes D_ge,c u (Sec. 3.4) in side order
-// S, E, N, W.
+// S, E, N, W.  Without g it returns sigma u - A u instead (the right side
+// of an implicit time step, Sec. 7.6), and without flux it skips the fluxes.
 template <int P>
 __global__ __launch_bounds__(256) void residual_kernel(
     const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
-    const double *__restrict__ uc, const double *__restrict__ g, double *__restrict__ r1,
-    double *__restrict__ flux, const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
+    const double *__restrict__ uc, const double *__restrict__ g, double sigma,
+    double *__restrict__ r1, double *__restrict__ flux, const double *__restrict__ Dh_g,
+    const double *__restrict__ Dh2_g,
     const double *__restrict__ Lloc_g, int q, int nrhs) {
   constexpr int PP = P * P, PI = P - 2, MI = PI * PI;
   __shared__ double u[PP], dx[PP], dy[PP], Dh[PP], Dh2[PP], cf[6][PP], Lloc[P * P];
@@ -63,9 +65,9 @@ __global__ __launch_bounds__(256) void residual_kernel(
                         cf[2][t] * sy * sy * uyy + cf[3][t] * sx * dx[t] + cf[4][t] * sy * dy[t] +
                         cf[5][t] * u[t];
       const int64_t o = (int64_t(r) * nl + leaf) * MI + a;
-      r1[o] = g[o] - Au;
+      r1[o] = (g ? g[o] : sigma * u[t]) - Au;
     }
-    for (int k = tid; k < 4 * q; k += 256) {
+    for (int k = flux ? tid : 4 * q; k < 4 * q; k += 256) {
       const int side = k / q, kk = k - side * q;
       double v = 0.0;
       for (int j = 0; j < P; ++j) {
@@ -171,30 +173,31 @@ static inline unsigned grid1(int64_t n) {
 }
 
 hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double *coef,
-                           const double *uc, const double *g, double *r1, double *flux,
+                           const double *uc, const double *g, double sigma, double *r1,
+                           double *flux,
                            const double *Dh, const double *Dh2, const double *Lloc, int q,
                            int nrhs, hipStream_t st) {
   dim3 grid(nleaf);
   switch (p) {
     case 16:
       hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
+                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 12:
       hipLaunchKernelGGL(residual_kernel<12>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
+                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 10:
       hipLaunchKernelGGL(residual_kernel<10>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
+                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 8:
       hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
+                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     case 6:
       hipLaunchKernelGGL(residual_kernel<6>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         r1, flux, Dh, Dh2, Lloc, q, nrhs);
+                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
       break;
     default:
       return hipErrorInvalidValue;

@@ -8,8 +8,11 @@
 
 namespace hps {
 
+// r1 = g - A u at interior nodes (g == nullptr: sigma u - A u); flux ==
+// nullptr skips the boundary fluxes
 hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double *coef,
-                           const double *uc, const double *g, double *r1, double *flux,
+                           const double *uc, const double *g, double sigma, double *r1,
+                           double *flux,
                            const double *Dh, const double *Dh2, const double *Lloc, int q,
                            int nrhs, hipStream_t st);
 hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb, int64_t n,

@@ -71,8 +71,34 @@ std::string refine_point(TreeDesc &t, int problem, double px, double py,
   return "";
 }
 
+std::string set_bc(TreeDesc &t, int problem, const int bc[4]) {
+  for (int s = 0; s < 4; ++s)
+    if (bc[s] < kBcDirichlet || bc[s] > kBcPeriodic) return "unknown side condition";
+  if ((bc[1] == kBcPeriodic) != (bc[3] == kBcPeriodic) ||
+      (bc[0] == kBcPeriodic) != (bc[2] == kBcPeriodic))
+    return "periodic sides come in opposite pairs";
+  if (problem < -1 || problem >= (int)t.probs.size()) return "bad problem index";
+  for (int k = 0; k < (int)t.probs.size(); ++k)
+    if (problem < 0 || k == problem)
+      for (int s = 0; s < 4; ++s) t.probs[k].bc[s] = bc[s];
+  return "";
+}
+
 std::string build_tree_boxes(const TreeDesc &t, Plan &pl) {
   pl.boxes.clear();
+  pl.general_bc = false;
+  for (const Problem &P : t.probs) {
+    const int64_t W = int64_t(P.nx) * kUnit, H = int64_t(P.ny) * kUnit;
+    for (int s = 0; s < 4; ++s) pl.general_bc |= P.bc[s] != kBcDirichlet;
+    // the box that closes a periodic seam must have two children that are
+    // not leaves (a leaf has one shared side)
+    if ((P.bc[1] == kBcPeriodic && P.nx < 4) || (P.bc[0] == kBcPeriodic && P.ny < 4))
+      return "a periodic direction needs at least 4 leaves";
+    for (const QuadLeaf &L : P.leaves)
+      if (L.depth > 0 && ((P.bc[1] == kBcPeriodic && (L.ix == 0 || L.ix + L.w == W)) ||
+                          (P.bc[0] == kBcPeriodic && (L.iy == 0 || L.iy + L.h == H))))
+        return "refined leaves on a periodic side";
+  }
   std::function<int(int, int64_t, int64_t, int64_t, int64_t, int, int)> make =
       [&](int prob, int64_t ix0, int64_t ix1, int64_t iy0, int64_t iy1,
           int kind, int depth) -> int {
@@ -125,8 +151,25 @@ std::string build_tree_boxes(const TreeDesc &t, Plan &pl) {
   };
   for (int pi = 0; pi < (int)t.probs.size(); ++pi) {
     const Problem &P = t.probs[pi];
-    if (make(pi, 0, int64_t(P.nx) * kUnit, 0, int64_t(P.ny) * kUnit, 0, 0) < 0)
-      return "tree construction failed";
+    const int64_t W = int64_t(P.nx) * kUnit, H = int64_t(P.ny) * kUnit;
+    bool neumann = false;
+    for (int s = 0; s < 4; ++s) neumann |= P.bc[s] == kBcNeumann;
+    int clo = -1;
+    if (neumann) {                      // the closure box precedes its root
+      clo = (int)pl.boxes.size();
+      pl.boxes.emplace_back();
+      Box &c = pl.boxes[clo];
+      c.problem = pi;
+      c.ix1 = W; c.iy1 = H;
+      c.kind = 3;
+    }
+    const int r = make(pi, 0, W, 0, H, 0, 0);
+    if (r < 0) return "tree construction failed";
+    if (clo >= 0) {
+      if (pl.boxes[r].leaf) return "a problem with a Neumann side needs at least two leaves";
+      pl.boxes[clo].alpha = r;
+      pl.boxes[r].parent = clo;
+    }
   }
   // canonical leaves
   pl.leaves.clear();
@@ -143,7 +186,8 @@ std::string build_tree_boxes(const TreeDesc &t, Plan &pl) {
   for (int i = (int)pl.boxes.size() - 1; i >= 0; --i) {
     Box &b = pl.boxes[i];
     b.height = b.leaf ? 0
-                      : 1 + std::max(pl.boxes[b.alpha].height, pl.boxes[b.beta].height);
+                      : 1 + std::max(pl.boxes[b.alpha].height,
+                                     b.beta >= 0 ? pl.boxes[b.beta].height : 0);
     pl.max_height = std::max(pl.max_height, b.height);
   }
   return "";
@@ -154,7 +198,15 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
   const std::vector<double> g = legendre_roots(q);
   std::map<SegKey, int> seg_id;
   pl.segs.clear();
-  auto seg = [&](int prob, const SideRef &s) {
+  // a periodic pair is one set of nodes: east sides onto west, north onto south
+  auto norm = [&](int prob, SideRef s) {
+    const Problem &P = t.probs[prob];
+    if (s.orient == 'v' && P.bc[1] == kBcPeriodic && s.fixed == int64_t(P.nx) * kUnit) s.fixed = 0;
+    if (s.orient == 'h' && P.bc[2] == kBcPeriodic && s.fixed == int64_t(P.ny) * kUnit) s.fixed = 0;
+    return s;
+  };
+  auto seg = [&](int prob, SideRef s) {
+    s = norm(prob, s);
     SegKey k{prob, s.orient, s.fixed, s.lo, s.hi};
     auto it = seg_id.find(k);
     if (it != seg_id.end()) return it->second;
@@ -170,7 +222,8 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
     const Segment &S = pl.segs[j / q];
     return double(S.s0) + double(S.s1 - S.s0) * (g[j % q] + 1.0) / 2.0;
   };
-  auto on_side = [&](int64_t j, int prob, const SideRef &s) {
+  auto on_side = [&](int64_t j, int prob, SideRef s) {
+    s = norm(prob, s);
     const Segment &S = pl.segs[j / q];
     return S.problem == prob && S.orient == s.orient && S.fixed == s.fixed &&
            S.s0 >= s.lo && S.s1 <= s.hi;
@@ -197,13 +250,56 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
   for (size_t pi = 0; pi < t.probs.size(); ++pi)
     for (const QuadLeaf &L : t.probs[pi].leaves) quads[pi].insert({L.ix, L.iy, L.w, L.h});
 
-  auto shared_side = [&](int id) -> int {
+  // sides whose nodes a box shares with its sibling, in block order: the
+  // side facing the sibling, then the periodic seam when the parent spans the
+  // whole periodic width across its cut; below a closure box, the Neumann
+  // sides in the order S, E, N, W
+  auto shared_sides = [&](int id) -> std::vector<int> {
     const Box &b = pl.boxes[id];
-    if (b.parent < 0) return -1;
+    if (b.parent < 0) return {};
     const Box &P = pl.boxes[b.parent];
-    bool is_a = P.alpha == id;
-    if (P.cut == 'x') return is_a ? 1 : 3;
-    return is_a ? 2 : 0;
+    const Problem &Pr = t.probs[b.problem];
+    std::vector<int> v;
+    if (P.kind == 3) {
+      for (int s = 0; s < 4; ++s)
+        if (Pr.bc[s] == kBcNeumann) v.push_back(s);
+      return v;
+    }
+    const bool is_a = P.alpha == id;
+    if (P.cut == 'x') {
+      v.push_back(is_a ? 1 : 3);
+      if (Pr.bc[1] == kBcPeriodic && P.ix0 == 0 && P.ix1 == int64_t(Pr.nx) * kUnit)
+        v.push_back(is_a ? 3 : 1);
+    } else {
+      v.push_back(is_a ? 2 : 0);
+      if (Pr.bc[2] == kBcPeriodic && P.iy0 == 0 && P.iy1 == int64_t(Pr.ny) * kUnit)
+        v.push_back(is_a ? 0 : 2);
+    }
+    return v;
+  };
+  // split cur into the kept nodes and the shared block (each side's nodes
+  // sorted along it)
+  auto split_shared = [&](int id, const std::vector<int64_t> &cur, std::vector<int64_t> &keep,
+                          std::vector<int64_t> &sh) {
+    const Box &b = pl.boxes[id];
+    const std::vector<int> sides = shared_sides(id);
+    keep.clear();
+    sh.clear();
+    std::vector<char> taken(cur.size(), 0);
+    for (int sd : sides) {
+      SideRef sr = box_side(b, sd);
+      std::vector<int64_t> part;
+      for (size_t a = 0; a < cur.size(); ++a)
+        if (!taken[a] && on_side(cur[a], b.problem, sr)) {
+          part.push_back(cur[a]);
+          taken[a] = 1;
+        }
+      std::sort(part.begin(), part.end(), [&](int64_t a, int64_t c) { return node_t(a) < node_t(c); });
+      sh.insert(sh.end(), part.begin(), part.end());
+    }
+    for (size_t a = 0; a < cur.size(); ++a)
+      if (!taken[a]) keep.push_back(cur[a]);
+    return (int)sides.size();
   };
 
   for (int id = (int)pl.boxes.size() - 1; id >= 0; --id) {
@@ -214,6 +310,15 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
         int sg = seg(b.problem, box_side(b, s));
         for (int k = 0; k < q; ++k) cur.push_back(int64_t(sg) * q + k);
       }
+      b.nat = cur;
+    } else if (b.kind == 3) {
+      // Neumann closure: the root's shared block (its Neumann nodes) is
+      // interior, the rest of its boundary stays exterior
+      const Box &A = pl.boxes[b.alpha];
+      const int m = A.n_shared;
+      if (m == 0) return "closure box without Neumann nodes";
+      b.gi.assign(A.fin.end() - m, A.fin.end());
+      cur.assign(A.fin.begin(), A.fin.end() - m);
       b.nat = cur;
     } else {
       const Box &A = pl.boxes[b.alpha], &B = pl.boxes[b.beta];
@@ -239,7 +344,7 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
         std::vector<Blk> blocks;
         for (int s = 0; s < 4; ++s) {
           if (!quads[b.problem].count({nb[s][0], nb[s][1], w, h})) continue;
-          SideRef sr = box_side(b, s);
+          SideRef sr = norm(b.problem, box_side(b, s));
           auto it = seg_id.find(SegKey{b.problem, sr.orient, sr.fixed, sr.lo, sr.hi});
           if (it == seg_id.end()) continue;
           Blk bl;
@@ -292,15 +397,8 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
         if (!blocks.empty()) {
           b.coarsened = true;
           // final order, then P_up (nat x fin) and P_down (fin x nat)
-          int ss = shared_side(id);
           std::vector<int64_t> keep, sh;
-          if (ss >= 0) {
-            SideRef sr = box_side(b, ss);
-            for (int64_t j : cur) (on_side(j, b.problem, sr) ? sh : keep).push_back(j);
-            std::sort(sh.begin(), sh.end(), [&](int64_t a, int64_t c) { return node_t(a) < node_t(c); });
-          } else {
-            keep = cur;
-          }
+          split_shared(id, cur, keep, sh);
           b.fin = keep;
           b.fin.insert(b.fin.end(), sh.begin(), sh.end());
           b.n_shared = (int)sh.size();
@@ -333,32 +431,34 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
         }
       }
     }
-    // final order: kept nodes, then the side shared with the sibling
-    int ss = shared_side(id);
+    // final order: kept nodes, then the side(s) shared with the sibling
     std::vector<int64_t> keep, sh;
-    if (ss >= 0) {
-      SideRef sr = box_side(b, ss);
-      for (int64_t j : cur) (on_side(j, b.problem, sr) ? sh : keep).push_back(j);
-      std::sort(sh.begin(), sh.end(), [&](int64_t a, int64_t c) { return node_t(a) < node_t(c); });
-    } else {
-      keep = cur;
-    }
+    const int nsides = split_shared(id, cur, keep, sh);
     b.fin = keep;
     b.fin.insert(b.fin.end(), sh.begin(), sh.end());
     b.n_shared = (int)sh.size();
-    if (b.leaf) b.role = ss < 0 ? 4 : ss;
+    if (b.leaf) {
+      if (nsides > 1) return "a leaf would share two sides (a periodic direction needs 4 leaves)";
+      b.role = nsides == 0 ? 4 : shared_sides(id)[0];
+    }
     std::unordered_map<int64_t, int> fpos;
     for (size_t a = 0; a < b.fin.size(); ++a) fpos[b.fin[a]] = (int)a;
     b.pi.resize(b.nat.size());
     for (size_t a = 0; a < b.nat.size(); ++a) b.pi[a] = fpos[b.nat[a]];
   }
-  // canonical domain boundary nodes
+  // canonical domain boundary nodes (a periodic side lists the seam nodes
+  // it shares with its partner)
   pl.bdry.clear();
+  pl.bdry_kind.clear();
   for (int pi = 0; pi < (int)t.probs.size(); ++pi) {
     const Problem &P = t.probs[pi];
     const int64_t W = int64_t(P.nx) * kUnit, H = int64_t(P.ny) * kUnit;
-    const std::pair<char, int64_t> sides[4] = {{'h', 0}, {'v', W}, {'h', H}, {'v', 0}};
-    for (auto &sd : sides) {
+    const std::pair<char, int64_t> sides[4] = {{'h', 0},
+                                               {'v', P.bc[1] == kBcPeriodic ? 0 : W},
+                                               {'h', P.bc[2] == kBcPeriodic ? 0 : H},
+                                               {'v', 0}};
+    for (int side = 0; side < 4; ++side) {
+      const auto &sd = sides[side];
       std::vector<int> ss;
       for (int s = 0; s < (int)pl.segs.size(); ++s)
         if (pl.segs[s].problem == pi && pl.segs[s].orient == sd.first &&
@@ -366,7 +466,10 @@ std::string plan_gauss(const TreeDesc &t, Plan &pl, int q) {
           ss.push_back(s);
       std::sort(ss.begin(), ss.end(), [&](int a, int c) { return pl.segs[a].s0 < pl.segs[c].s0; });
       for (int s : ss)
-        for (int k = 0; k < q; ++k) pl.bdry.push_back(int64_t(s) * q + k);
+        for (int k = 0; k < q; ++k) {
+          pl.bdry.push_back(int64_t(s) * q + k);
+          pl.bdry_kind.push_back((int8_t)P.bc[side]);
+        }
     }
   }
   // leaf size classes

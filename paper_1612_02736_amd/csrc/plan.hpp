@@ -5,6 +5,16 @@
 // figure (J1, J2, J3), Sec. 5.1 (global Gauss vector), Sec. 6.1 (refinement
 // criterion), Sec. 6.2-6.4 (neighbours, P_up / P_down).
 //
+// Side conditions (Sec. 7.6): every side of a problem is Dirichlet, Neumann
+// or periodic (opposite pairs).  A periodic pair shares one set of Gauss
+// nodes (the east / north segments are stored as the west / south ones), so
+// the seam is eliminated by the merge whose children meet across it: the box
+// spanning the whole periodic width, cut across it, whose children then each
+// carry two shared blocks (the cut, then the seam).  A problem with Neumann
+// sides gets one more box above its root (kind 3, no beta) whose interior
+// nodes are the Neumann nodes: its "merge" with a zero-T sibling solves the
+// root's flux relation on them.
+//
 // Orders used on the device (all matrices column-major):
 //  * a box's "natural" boundary order: leaf S,E,N,W; parent J1 then J2;
 //  * its "final" order: the nodes it keeps after its parent's merge first,
@@ -31,10 +41,13 @@ struct QuadLeaf {
   }
 };
 
+enum { kBcDirichlet = 0, kBcNeumann = 1, kBcPeriodic = 2 };
+
 struct Problem {
   double X0, X1, Y0, Y1;
   int nx, ny;
   std::set<QuadLeaf> leaves;
+  int bc[4] = {kBcDirichlet, kBcDirichlet, kBcDirichlet, kBcDirichlet};  // S, E, N, W
 };
 
 struct TreeDesc {
@@ -44,7 +57,8 @@ struct TreeDesc {
 struct Box {
   int problem = 0;
   int64_t ix0 = 0, ix1 = 0, iy0 = 0, iy1 = 0;
-  int kind = 0;  // 0 base region, 1 refined quad box, 2 half of a quad box
+  int kind = 0;  // 0 base region, 1 refined quad box, 2 half of a quad box,
+                 // 3 Neumann closure above a root (alpha = root, no beta)
   int depth = 0;
   int parent = -1, alpha = -1, beta = -1;
   char cut = 0;
@@ -78,6 +92,8 @@ struct Plan {
   std::vector<Segment> segs;
   int64_t n_gauss = 0;
   std::vector<int64_t> bdry;        // canonical boundary node ids
+  std::vector<int8_t> bdry_kind;    // kBc* of each canonical boundary entry
+  bool general_bc = false;          // some side is not Dirichlet
   std::vector<double> node_xy;      // [n_gauss][2]
   int max_height = 0;
   // leaf size classes
@@ -91,5 +107,6 @@ void leaf_phys(const TreeDesc &t, const Box &b, double &x0, double &x1,
                double &y0, double &y1);
 std::string refine_point(TreeDesc &t, int problem, double px, double py,
                          int n_ref, double tfac);
+std::string set_bc(TreeDesc &t, int problem, const int bc[4]);
 
 }  // namespace hps

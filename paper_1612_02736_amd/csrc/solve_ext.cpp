@@ -60,6 +60,8 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
   if (!H->has_fp32) return fail(HPS_EINVAL, "mixed precision needs a build with keep_fp32");
   if (!H->conforming)
     return fail(HPS_EINVAL, "mixed precision is available on trees without refined interfaces");
+  if (H->pl.general_bc)
+    return fail(HPS_EINVAL, "mixed precision is available for Dirichlet problems");
   int rc = ext_buffers(H, nrhs);
   if (rc) return rc;
   SolveExt &E = *H->ext;
@@ -80,7 +82,7 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
   int it = 0;
   double ratio = 1.0;
   for (; it < max_iter; ++it) {
-    HIPCHK(launch_residual(H->p, H->d_leaf.p, H->nleaf, H->coef.p, u, g, E.r1.p, E.flux.p,
+    HIPCHK(launch_residual(H->p, H->d_leaf.p, H->nleaf, H->coef.p, u, g, 0.0, E.r1.p, E.flux.p,
                            H->aux.p + H->Dh_off, H->aux.p + H->Dh2_off, H->d_lloc.p, H->q, nrhs,
                            st));
     HIPCHK(launch_jump(H->d_jn.p, H->d_fa.p, H->d_fb.p, H->n_jump, E.flux.p,
@@ -112,6 +114,7 @@ extern "C" int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs, do
   if (!h || !ubar || !fbar || !gbar) return fail(HPS_EINVAL, "NULL argument");
   if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
   if (h->econ) return fail(HPS_EINVAL, "the adjoint needs the stored leaf operators F");
+  if (h->pl.general_bc) return fail(HPS_EINVAL, "the adjoint is available for Dirichlet problems");
   hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
   int rc = ensure_solve_buffers(h, nrhs);
   if (rc) return rc;
@@ -133,6 +136,17 @@ extern "C" int hps_coeff_grad_c(hps_handle *h, const double *u, const double *gb
   if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(launch_cbar(u, gbar, cbar, h->p, h->nleaf, nrhs, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
+}
+
+extern "C" int hps_apply_operator(hps_handle *h, const double *u, int nrhs, double sigma,
+                                  double *out, void *stream) {
+  if (!h || !u || !out) return fail(HPS_EINVAL, "NULL argument");
+  if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_residual(h->p, h->d_leaf.p, h->nleaf, h->coef.p, u, nullptr, sigma, out, nullptr,
+                         h->aux.p + h->Dh_off, h->aux.p + h->Dh2_off, h->d_lloc.p, h->q, nrhs, st));
   HIPCHK(hipStreamSynchronize(st));
   return HPS_OK;
 }

@@ -15,16 +15,18 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhps.so")
 
 HPS_PREC_FP64, HPS_PREC_MIXED, HPS_PREC_FP32 = 0, 1, 2
+HPS_BC_DIRICHLET, HPS_BC_NEUMANN, HPS_BC_PERIODIC = 0, 1, 2
+_BC_CODES = {"D": HPS_BC_DIRICHLET, "N": HPS_BC_NEUMANN, "P": HPS_BC_PERIODIC}
 _ERRS = {-1: "HPS_EINVAL", -2: "HPS_ETREE", -3: "HPS_ESINGULAR",
          -4: "HPS_ENONFINITE", -5: "HPS_ENOCONV", -6: "HPS_EHIP", -7: "HPS_ENOMEM"}
 
-EXPORTS = ["hps_tree_uniform", "hps_tree_refine_point", "hps_tree_info",
+EXPORTS = ["hps_tree_uniform", "hps_tree_refine_point", "hps_tree_set_bc", "hps_tree_info",
            "hps_tree_counts", "hps_leaf_cheb_nodes", "hps_leaf_boxes",
            "hps_bdry_gauss_nodes", "hps_gauss_nodes", "hps_tree_free",
            "hps_build", "hps_refactor", "hps_build_workspace_size",
            "hps_build_workspace_size_econ", "hps_build_workspace_size_opts", "hps_solve",
-           "hps_solve_adjoint", "hps_coeff_grad_c", "hps_handle_free",
-           "hps_last_error"]
+           "hps_solve_adjoint", "hps_coeff_grad_c", "hps_apply_operator",
+           "hps_handle_free", "hps_last_error"]
 
 
 class HPSError(RuntimeError):
@@ -66,6 +68,7 @@ def lib():
     vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     L.hps_tree_uniform.argtypes = [dp, dp, dp, dp, ip, ip, ip, ctypes.POINTER(vp)]
     L.hps_tree_refine_point.argtypes = [vp, ip, dp, dp, ip, dp]
+    L.hps_tree_set_bc.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     L.hps_tree_info.argtypes = [vp, ctypes.POINTER(TreeInfo)]
     L.hps_tree_counts.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -86,6 +89,7 @@ def lib():
     L.hps_solve.argtypes = [vp, vp, vp, ip, vp, ctypes.POINTER(SolveOpts)]
     L.hps_solve_adjoint.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(SolveOpts)]
     L.hps_coeff_grad_c.argtypes = [vp, vp, vp, ip, vp, vp]
+    L.hps_apply_operator.argtypes = [vp, vp, ip, dp, vp, vp]
     L.hps_handle_free.argtypes = [vp]
     L.hps_handle_free.restype = None
     L.hps_last_error.restype = ctypes.c_char_p
@@ -127,6 +131,17 @@ class Tree:
 
     def refine_point(self, problem, px, py, n_ref, t=np.sqrt(2.0)):
         _check(lib().hps_tree_refine_point(self._h, problem, px, py, n_ref, t))
+        return self
+
+    def set_bc(self, bc, problem=-1):
+        """Side conditions of sides S, E, N, W: a string such as "NPNP" (D
+        Dirichlet, N Neumann, P periodic) or four HPS_BC_* codes;
+        problem=-1: every problem."""
+        codes = [_BC_CODES[c] if isinstance(c, str) else int(c) for c in bc]
+        if len(codes) != 4:
+            raise ValueError("bc needs four sides")
+        arr = (ctypes.c_int * 4)(*codes)
+        _check(lib().hps_tree_set_bc(self._h, problem, arr))
         return self
 
     def info(self):
@@ -246,6 +261,19 @@ class Solver:
                                        _dev_ptr(fb, "fbar"), _dev_ptr(gb, "gbar"),
                                        ctypes.byref(o)))
         return fb, gb
+
+    def apply_operator(self, u, sigma, stream=None):
+        """sigma u - A u at the interior nodes: u [nrhs, n_leaves, p^2] ->
+        [nrhs, n_leaves, (p-2)^2] (the right side of an implicit step)."""
+        torch = self._torch
+        nrhs = u.shape[0]
+        if tuple(u.shape) != (nrhs, self.n_leaves, self.p * self.p):
+            raise ValueError("u has the wrong shape")
+        out = torch.empty((nrhs, self.n_leaves, (self.p - 2) ** 2), dtype=torch.float64,
+                          device=self.device)
+        _check(lib().hps_apply_operator(self._h, _dev_ptr(u, "u"), nrhs, float(sigma),
+                                        _dev_ptr(out, "out"), _stream(stream)))
+        return out
 
     def coeff_grad_c(self, u, gbar, stream=None):
         torch = self._torch

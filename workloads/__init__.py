@@ -276,3 +276,13 @@ def side_data(sol, xy, kinds, rect):
     flux = np.where(horiz, uy, ux)
     kinds = np.asarray(kinds)
     return np.where(kinds == "D", u, np.where(kinds == "N", flux, 0.0))
+
+
+def convdiff_smooth_initial(x, y, beta=12.0, xhat=CD_XHAT):
+    """A bump near xhat that fits the side conditions of the Sec. 7.6
+    problem: periodic in x, and even about y = 0 and y = 1 (so every odd
+    y-derivative, the Neumann data included, vanishes there)."""
+    bx = np.exp(beta * (np.cos(TWO_PI * (x - xhat[0])) - 1.0))
+    by = (np.exp(beta * (np.cos(np.pi * (y - xhat[1])) - 1.0)) +
+          np.exp(beta * (np.cos(np.pi * (y + xhat[1])) - 1.0)))
+    return bx * by
