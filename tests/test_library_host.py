@@ -40,19 +40,29 @@ def test_every_declared_symbol_is_exported(header):
     assert not missing, missing
 
 
-@pytest.mark.parametrize("nx,ny,nprob,refine", [
-    (4, 4, 1, None), (3, 5, 1, None), (2, 2, 3, None),
-    (4, 4, 1, (0, 0.25, 0.75, 1)), (4, 4, 1, (0, 0.37, 0.61, 3)),
-    (2, 2, 2, (1, 0.8, 0.3, 2))])
-def test_geometry_matches_oracle(nx, ny, nprob, refine):
+@pytest.mark.parametrize("nx,ny,nprob,refine,bc", [
+    (4, 4, 1, None, None), (3, 5, 1, None, None), (2, 2, 3, None, None),
+    (4, 4, 1, (0, 0.25, 0.75, 1), None), (4, 4, 1, (0, 0.37, 0.61, 3), None),
+    (2, 2, 2, (1, 0.8, 0.3, 2), None),
+    (4, 4, 1, None, "NPNP"), (5, 4, 1, None, "PPPP"), (4, 6, 2, None, "PNPN"),
+    (3, 4, 1, (0, 0.4, 0.5, 2), "NNNN"), (4, 4, 1, (0, 0.5, 0.5, 1), "DPDP")])
+def test_geometry_matches_oracle(nx, ny, nprob, refine, bc):
+    """Leaf grids, Gauss node numbering and the canonical boundary list agree
+    with the oracle's, including trees with Neumann and periodic sides (a
+    problem with a Neumann side has one more box in the library: the closure
+    above its root)."""
     H = _H()
     t = H.Tree(0.0, 1.0, 0.0, 1.0, nx, ny, nprob)
     ot = oracle.Tree.uniform(0.0, 1.0, 0.0, 1.0, nx, ny, nprob)
+    if bc:
+        t.set_bc(bc)
+        ot.set_bc(bc)
     if refine:
         t.refine_point(*refine)
         ot.refine_point(*refine)
     assert t.n_leaves == len(ot.leaves)
-    assert t.info()["n_boxes"] == len(ot.boxes)
+    closures = nprob if bc and "N" in bc else 0
+    assert t.info()["n_boxes"] == len(ot.boxes) + closures
     for p in (8, 16):
         np.testing.assert_allclose(t.leaf_cheb_nodes(p), leaf_nodes(ot, p), atol=2e-16)
     q = 7
