@@ -15,9 +15,10 @@ namespace hps {
 // coefficients and reference matrices are read once).  Residual of the
 // collocated PDE at interior nodes, r = g - A u (Sec. 3.2, same A as the
 // build), and the leaf's boundary fluxes D_ge,c u (Sec. 3.4) in side order
-// S, E, N, W.  Without g it returns sigma u - A u instead (the right side
-// of an implicit time step, Sec. 7.6), and without flux it skips the fluxes.
-template <int P>
+// S, E, N, W.  SHIFT = true returns sigma u - A u instead and no fluxes (the
+// right side of an implicit time step, Sec. 7.6); it is a separate
+// instantiation so that the residual keeps its register budget.
+template <int P, bool SHIFT>
 __global__ __launch_bounds__(256) void residual_kernel(
     const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
     const double *__restrict__ uc, const double *__restrict__ g, double sigma,
@@ -65,9 +66,10 @@ __global__ __launch_bounds__(256) void residual_kernel(
                         cf[2][t] * sy * sy * uyy + cf[3][t] * sx * dx[t] + cf[4][t] * sy * dy[t] +
                         cf[5][t] * u[t];
       const int64_t o = (int64_t(r) * nl + leaf) * MI + a;
-      r1[o] = (g ? g[o] : sigma * u[t]) - Au;
+      if constexpr (SHIFT) r1[o] = sigma * u[t] - Au;
+      else r1[o] = g[o] - Au;
     }
-    for (int k = flux ? tid : 4 * q; k < 4 * q; k += 256) {
+    for (int k = SHIFT ? 4 * q : tid; k < 4 * q; k += 256) {
       const int side = k / q, kk = k - side * q;
       double v = 0.0;
       for (int j = 0; j < P; ++j) {
@@ -172,37 +174,41 @@ static inline unsigned grid1(int64_t n) {
   return unsigned(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
-hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double *coef,
-                           const double *uc, const double *g, double sigma, double *r1,
-                           double *flux,
-                           const double *Dh, const double *Dh2, const double *Lloc, int q,
-                           int nrhs, hipStream_t st) {
+template <bool SHIFT>
+static hipError_t launch_residual_t(int p, const LeafDesc *leafd, int nleaf, const double *coef,
+                                    const double *uc, const double *g, double sigma, double *r1,
+                                    double *flux, const double *Dh, const double *Dh2,
+                                    const double *Lloc, int q, int nrhs, hipStream_t st) {
   dim3 grid(nleaf);
   switch (p) {
-    case 16:
-      hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
+#define HPS_RES_CASE(PV)                                                                      \
+    case PV:                                                                                  \
+      hipLaunchKernelGGL((residual_kernel<PV, SHIFT>), grid, dim3(256), 0, st, leafd, nleaf,  \
+                         coef, uc, g, sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);               \
       break;
-    case 12:
-      hipLaunchKernelGGL(residual_kernel<12>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
-      break;
-    case 10:
-      hipLaunchKernelGGL(residual_kernel<10>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
-      break;
-    case 8:
-      hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
-      break;
-    case 6:
-      hipLaunchKernelGGL(residual_kernel<6>, grid, dim3(256), 0, st, leafd, nleaf, coef, uc, g,
-                         sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
-      break;
+    HPS_RES_CASE(16)
+    HPS_RES_CASE(12)
+    HPS_RES_CASE(10)
+    HPS_RES_CASE(8)
+    HPS_RES_CASE(6)
+#undef HPS_RES_CASE
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double *coef,
+                           const double *uc, const double *g, double sigma, double *r1,
+                           double *flux, const double *Dh, const double *Dh2, const double *Lloc,
+                           int q, int nrhs, hipStream_t st) {
+  if (g) {
+    if (!flux) return hipErrorInvalidValue;
+    return launch_residual_t<false>(p, leafd, nleaf, coef, uc, g, sigma, r1, flux, Dh, Dh2, Lloc,
+                                    q, nrhs, st);
+  }
+  return launch_residual_t<true>(p, leafd, nleaf, coef, uc, g, sigma, r1, flux, Dh, Dh2, Lloc,
+                                 q, nrhs, st);
 }
 
 hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb, int64_t n,

@@ -8,8 +8,8 @@
 
 namespace hps {
 
-// r1 = g - A u at interior nodes (g == nullptr: sigma u - A u); flux ==
-// nullptr skips the boundary fluxes
+// r1 = g - A u at interior nodes and the boundary fluxes into flux; with
+// g == nullptr, r1 = sigma u - A u and no fluxes (flux is not used)
 hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double *coef,
                            const double *uc, const double *g, double sigma, double *r1,
                            double *flux,
