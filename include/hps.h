@@ -133,8 +133,9 @@ int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
  * direction needs at least 4 leaves and no refined leaf on its sides; a
  * problem with a Neumann side needs at least 2 leaves; a problem without a
  * Dirichlet side needs q <= p - 2 (with q = p - 1 its discrete system is
- * singular).  Handles of trees with a non-Dirichlet side solve in FP64 or
- * FP32 only (no HPS_PREC_MIXED, no adjoint, no translation_invariant).
+ * singular).  Handles of trees with a non-Dirichlet side have no adjoint and
+ * no translation_invariant build; HPS_PREC_MIXED refines against the
+ * residual's flux rows at the periodic seams and the Neumann nodes too.
  * Errors: HPS_EINVAL (unknown code, unpaired periodic side, bad problem). */
 enum { HPS_BC_DIRICHLET = 0, HPS_BC_NEUMANN = 1, HPS_BC_PERIODIC = 2 };
 int hps_tree_set_bc(hps_tree *tree, int problem, const int *bc);

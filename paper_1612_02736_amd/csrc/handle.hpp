@@ -107,9 +107,9 @@ struct hps_handle {
   hps::DevArray<hps::VecOpDesc> d_vecop;
   // flux-jump residual maps (uniform trees): interior node id, flux index of
   // the west/south leaf and of the east/north leaf
-  hps::DevArray<int32_t> d_jn, d_fa, d_fb;
+  hps::DevArray<int32_t> d_jn, d_fa, d_fb, d_fp;
   int64_t iota_off = 0;            // imap offset of the identity map
-  std::vector<int32_t> h_jn, h_fa, h_fb;   // host copies, uploaded by hps_build
+  std::vector<int32_t> h_jn, h_fa, h_fb, h_fp;   // host copies, uploaded by hps_build
   std::vector<double> h_lloc;
   int64_t n_jump = 0;
   bool conforming = true;     // no refined interfaces

@@ -871,6 +871,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
           ApplyDesc a = ad(m, m, 0, 1, Lo.X[b], m);
           a.B1 = vref(BUF_IN0, 0, Lo.map_psi[b], H->n_bdry);
           a.B2 = vref(BUF_VEC, Lo.h[B.alpha] + n1, -1, kInterleaved);
+          a.B3 = vref(BUF_AUX, 0, Lo.map_gi[b], kInterleaved);  // Neumann-row residual
+          a.B3.buf = -1;                                          // off unless enabled
           a.C = vref(BUF_VEC, Lo.w[b], -1, kInterleaved);
           wst.push_back(a);
           continue;
@@ -1201,7 +1203,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     bool conf = true;
     for (const Box &B : pl.boxes) if (B.coarsened) conf = false;
     H->conforming = conf;
-    std::vector<int32_t> jn, fa, fb;
+    std::vector<int32_t> jn, fa, fb, fp;
     if (conf) {
       // owner (leaf index, natural position) of each node on each side
       std::vector<int64_t> own_a(pl.n_gauss, -1), own_b(pl.n_gauss, -1);
@@ -1215,17 +1217,38 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
           else own_b[j] = int64_t(i) * g4 + k;
         }
       }
+      // a periodic seam is eliminated by a merge whose alpha lies on the
+      // seam's west (south) side, where its leaves see the node on their W
+      // (S) side: the two roles are swapped there
+      for (int64_t j = 0; j < pl.n_gauss; ++j) {
+        const Segment &S = pl.segs[j / q];
+        const Problem &P = H->tree.probs[S.problem];
+        const bool seam = S.fixed == 0 && ((S.orient == 'v' && P.bc[1] == kBcPeriodic) ||
+                                           (S.orient == 'h' && P.bc[2] == kBcPeriodic));
+        if (seam) std::swap(own_a[j], own_b[j]);
+      }
       for (int64_t j = 0; j < pl.n_gauss; ++j)
         if (own_a[j] >= 0 && own_b[j] >= 0) {
           jn.push_back((int32_t)j);
           fa.push_back((int32_t)own_a[j]);
           fb.push_back((int32_t)own_b[j]);
+          fp.push_back(-1);
         }
+      // a Neumann node's row reads flux = psi: its residual is psi - flux
+      for (size_t k = 0; k < pl.bdry.size(); ++k) {
+        if (pl.bdry_kind[k] != kBcNeumann) continue;
+        const int64_t j = pl.bdry[k];
+        jn.push_back((int32_t)j);
+        fa.push_back((int32_t)(own_a[j] >= 0 ? own_a[j] : own_b[j]));
+        fb.push_back(-1);
+        fp.push_back((int32_t)k);
+      }
     }
     H->n_jump = (int64_t)jn.size();
     H->h_jn = std::move(jn);
     H->h_fa = std::move(fa);
     H->h_fb = std::move(fb);
+    H->h_fp = std::move(fp);
     std::vector<double> xc = cheb_points(p), xg = legendre_roots(q);
     H->h_lloc = interp_matrix(xc, xg);
   }
@@ -1487,6 +1510,7 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   HIPCHK(H->d_jn.upload(H->h_jn));
   HIPCHK(H->d_fa.upload(H->h_fa));
   HIPCHK(H->d_fb.upload(H->h_fb));
+  HIPCHK(H->d_fp.upload(H->h_fp));
   HIPCHK(H->d_lloc.upload(H->h_lloc));
   // keep the coefficients (residuals of mixed-precision solves use them)
   const size_t ncoef = size_t(H->nleaf) * 6 * p * p;

@@ -85,21 +85,26 @@ __global__ __launch_bounds__(256) void residual_kernel(
   }
 }
 
-// jump(node) = flux of the east/north leaf - flux of the west/south leaf,
-// written RHS-interleaved: jump[node * nrhs + r]
+// Residual of the flux rows, written RHS-interleaved (jump[node * nrhs + r]):
+// at an interior node, the beta side's leaf flux minus the alpha side's
+// (fb, fa); at a Neumann node (fb < 0), the data psi (f[fp]) minus the leaf
+// flux.
 __global__ __launch_bounds__(256) void jump_kernel(const int32_t *__restrict__ jn,
                                                    const int32_t *__restrict__ fa,
-                                                   const int32_t *__restrict__ fb, int64_t n,
+                                                   const int32_t *__restrict__ fb,
+                                                   const int32_t *__restrict__ fp, int64_t n,
                                                    const double *__restrict__ flux,
-                                                   int64_t flux_stride, double *__restrict__ jump,
+                                                   int64_t flux_stride,
+                                                   const double *__restrict__ f,
+                                                   int64_t f_stride, double *__restrict__ jump,
                                                    int nrhs) {
   const int64_t tot = n * nrhs;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot;
        e += int64_t(gridDim.x) * blockDim.x) {
     const int r = int(e / n);
     const int64_t i = e - int64_t(r) * n;
-    jump[int64_t(jn[i]) * nrhs + r] =
-        flux[r * flux_stride + fb[i]] - flux[r * flux_stride + fa[i]];
+    const double other = fb[i] >= 0 ? flux[r * flux_stride + fb[i]] : f[r * f_stride + fp[i]];
+    jump[int64_t(jn[i]) * nrhs + r] = other - flux[r * flux_stride + fa[i]];
   }
 }
 
@@ -211,12 +216,13 @@ hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double
                                  q, nrhs, st);
 }
 
-hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb, int64_t n,
-                       const double *flux, int64_t flux_stride, double *jump, int nrhs,
+hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb,
+                       const int32_t *fp, int64_t n, const double *flux, int64_t flux_stride,
+                       const double *f, int64_t f_stride, double *jump, int nrhs,
                        hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jump_kernel, dim3(grid1(n * nrhs)), dim3(256), 0, st, jn, fa, fb, n, flux,
-                     flux_stride, jump, nrhs);
+  hipLaunchKernelGGL(jump_kernel, dim3(grid1(n * nrhs)), dim3(256), 0, st, jn, fa, fb, fp, n,
+                     flux, flux_stride, f, f_stride, jump, nrhs);
   return hipGetLastError();
 }
 

@@ -15,8 +15,9 @@ hipError_t launch_residual(int p, const LeafDesc *leafd, int nleaf, const double
                            double *flux,
                            const double *Dh, const double *Dh2, const double *Lloc, int q,
                            int nrhs, hipStream_t st);
-hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb, int64_t n,
-                       const double *flux, int64_t flux_stride, double *jump, int nrhs,
+hipError_t launch_jump(const int32_t *jn, const int32_t *fa, const int32_t *fb,
+                       const int32_t *fp, int64_t n, const double *flux, int64_t flux_stride,
+                       const double *f, int64_t f_stride, double *jump, int nrhs,
                        hipStream_t st);
 hipError_t launch_accumulate(double *x, int64_t xs, double *y, int64_t ys, int64_t n, int nrhs,
                              int copy_back, hipStream_t st);

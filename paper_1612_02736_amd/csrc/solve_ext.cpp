@@ -60,8 +60,6 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
   if (!H->has_fp32) return fail(HPS_EINVAL, "mixed precision needs a build with keep_fp32");
   if (!H->conforming)
     return fail(HPS_EINVAL, "mixed precision is available on trees without refined interfaces");
-  if (H->pl.general_bc)
-    return fail(HPS_EINVAL, "mixed precision is available for Dirichlet problems");
   int rc = ext_buffers(H, nrhs);
   if (rc) return rc;
   SolveExt &E = *H->ext;
@@ -85,8 +83,8 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
     HIPCHK(launch_residual(H->p, H->d_leaf.p, H->nleaf, H->coef.p, u, g, 0.0, E.r1.p, E.flux.p,
                            H->aux.p + H->Dh_off, H->aux.p + H->Dh2_off, H->d_lloc.p, H->q, nrhs,
                            st));
-    HIPCHK(launch_jump(H->d_jn.p, H->d_fa.p, H->d_fb.p, H->n_jump, E.flux.p,
-                       int64_t(H->nleaf) * H->g4, E.jump.p, nrhs, st));
+    HIPCHK(launch_jump(H->d_jn.p, H->d_fa.p, H->d_fb.p, H->d_fp.p, H->n_jump, E.flux.p,
+                       int64_t(H->nleaf) * H->g4, f, H->n_bdry, E.jump.p, nrhs, st));
     rc = hps_solve_pass(H, E.zf.p, E.r1.p, nrhs, E.duc.p, 1, E.jump.p, st);
     if (rc) return rc;
     HIPCHK(launch_accumulate(E.xug.p, 0, vug, 0, nug, 1, 1, st));

@@ -175,17 +175,73 @@ def test_side_condition_refusals():
     with pytest.raises(H.HPSError, match="Dirichlet sides"):
         H.Solver(t, coeffs, p, p - 2, translation_invariant=True)
     s = H.Solver(t, coeffs, p, p - 2, keep_fp32=True)
-    nb = s.n_bdry
-    f = to_dev(np.zeros((1, nb)))
-    g = to_dev(np.zeros((1, t.n_leaves, (p - 2) ** 2)))
-    with pytest.raises(H.HPSError, match="Dirichlet problems"):
-        s.solve(f, g, precision=H.HPS_PREC_MIXED)
     with pytest.raises(H.HPSError, match="Dirichlet problems"):
         s.solve_adjoint(to_dev(np.zeros((1, t.n_leaves, p * p))))
     with pytest.raises(H.HPSError, match="opposite pairs"):
         H.Tree(0, 1, 0, 1, 4, 4).set_bc("PDDD")
     # a Dirichlet side allows q = p - 1
     H.Solver(H.Tree(0, 1, 0, 1, 4, 4).set_bc("NPDP"), coeffs, p, p - 1)
+
+
+@pytest.mark.parametrize("bc,nx,ny,p,q,nrhs", [
+    ("NPNP", 8, 8, 16, 14, 4),
+    ("PPPP", 4, 4, 12, 10, 2),
+    ("NNNN", 4, 6, 12, 10, 1),
+    ("DNDN", 4, 4, 16, 15, 16),
+])
+def test_mixed_precision_with_side_conditions(bc, nx, ny, p, q, nrhs):
+    """FP32 sweeps refined against the FP64 residual, whose flux rows include
+    the periodic seams (oriented by the merge that eliminates them) and the
+    Neumann rows (data minus leaf flux): within 1e-10 of the oracle, while
+    one FP32 sweep alone is not."""
+    import torch
+    H = _lib()
+    print(f"mixed {bc} {nx}x{ny} p={p} q={q} nrhs={nrhs}", flush=True)
+    t = H.Tree(0, 1, 0, 1, nx, ny).set_bc(bc)
+    ot = oracle.Tree.uniform(0, 1, 0, 1, nx, ny)
+    ot.set_bc(bc)
+    sols = [W.FourierSolution(80 + r) for r in range(nrhs)]
+    coeffs, _, _, _ = _lib_case(t, p, q, sols[0], bc)
+    F = np.stack([_lib_case(t, p, q, s_, bc)[1] for s_ in sols])
+    G = np.stack([_lib_case(t, p, q, s_, bc)[2] for s_ in sols])
+    s = H.Solver(t, to_dev(coeffs), p, q, keep_fp32=True)
+    stats = {}
+    um = s.solve(to_dev(F), to_dev(G), precision=H.HPS_PREC_MIXED, stats=stats).cpu().numpy()
+    u32 = s.solve(to_dev(F), to_dev(G), precision=H.HPS_PREC_FP32).cpu().numpy()
+    torch.cuda.synchronize()
+    ops = oracle.build(ot, coeffs, p, q)
+    nxy, bdry = ot.gauss(q)
+    for r in (0, nrhs - 1):
+        fo = W.side_data(sols[r], nxy[bdry], ot.bdry_kind(q), (0, 1, 0, 1))
+        uo, _ = oracle.solve(ops, fo, _oracle_g(ot, coeffs, p, sols[r]))
+        em, e32 = relerr(um[r], uo), relerr(u32[r], uo)
+        print(f"  rhs {r}: mixed {em:.2e} ({stats}), one FP32 sweep {e32:.2e}", flush=True)
+        assert em <= 1e-10
+        assert e32 > 1e-9
+
+
+def test_crank_nicolson_mixed_precision():
+    """The Sec. 7.6 workload (16 x 16 leaves, p = 16, q = 14) stepped with
+    mixed-precision solves agrees with the FP64 stepping to 1e-10 after 8
+    steps."""
+    import torch
+    H = _lib()
+    k, steps = 0.05, 8
+    t = H.Tree(0, 1, 0, 1, 16, 16).set_bc("NPNP")
+    xy = t.leaf_cheb_nodes(16)
+    X, Y = xy[..., 0], xy[..., 1]
+    coeffs = np.stack([W.convdiff_coeffs(X[i], Y[i], k) for i in range(len(xy))])
+    s = H.Solver(t, to_dev(coeffs), 16, 14, keep_fp32=True)
+    f = to_dev(np.zeros((1, s.n_bdry)))
+    u0 = to_dev(W.convdiff_initial(X, Y)[None])
+    u64, umx = u0, u0
+    for _ in range(steps):
+        u64 = s.solve(f, s.apply_operator(u64, 2.0 / k))
+        umx = s.solve(f, s.apply_operator(umx, 2.0 / k), precision=H.HPS_PREC_MIXED)
+    torch.cuda.synchronize()
+    err = relerr(umx.cpu().numpy(), u64.cpu().numpy())
+    print(f"CN mixed vs FP64 after {steps} steps: {err:.2e}", flush=True)
+    assert err <= 1e-10
 
 
 def test_apply_operator_matches_oracle():
