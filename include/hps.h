@@ -133,9 +133,10 @@ int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
  * direction needs at least 4 leaves and no refined leaf on its sides; a
  * problem with a Neumann side needs at least 2 leaves; a problem without a
  * Dirichlet side needs q <= p - 2 (with q = p - 1 its discrete system is
- * singular).  Handles of trees with a non-Dirichlet side have no adjoint and
- * no translation_invariant build; HPS_PREC_MIXED refines against the
- * residual's flux rows at the periodic seams and the Neumann nodes too.
+ * singular).  Trees with a non-Dirichlet side have no translation_invariant
+ * build; HPS_PREC_MIXED refines against the residual's flux rows at the
+ * periodic seams and the Neumann nodes too, and hps_solve_adjoint returns
+ * fbar = d/dpsi at Neumann entries and 0 at periodic entries.
  * Errors: HPS_EINVAL (unknown code, unpaired periodic side, bad problem). */
 enum { HPS_BC_DIRICHLET = 0, HPS_BC_NEUMANN = 1, HPS_BC_PERIODIC = 2 };
 int hps_tree_set_bc(hps_tree *tree, int problem, const int *bc);
@@ -215,7 +216,8 @@ int hps_solve(hps_handle *h, const double *f, const double *g, int nrhs,
  * paper): given ubar [nrhs][n_leaves][p*p] (device) returns
  * fbar [nrhs][n_bdry] and gbar [nrhs][n_leaves][(p-2)^2] (device) by the
  * transposed sweeps, reusing the stored operators (HPS_EINVAL on an economic
- * build, which keeps no F). */
+ * build, which keeps no F).  Entries of fbar on periodic sides are 0 (their
+ * data is not used). */
 int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs,
                       double *fbar, double *gbar, const hps_solve_opts *opts);
 

@@ -1029,11 +1029,13 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     apply_step(tmp, H->ext_prog);
   }
   // adjoint, reverse of the downward pass (children before parents):
-  // inputs ubar (BUF_IN0), outputs fbar (BUF_IN1) and gbar (BUF_IN2);
-  // Dirichlet problems only (no closure boxes, no periodic seams)
+  // inputs ubar (BUF_IN0), outputs fbar (BUF_IN1) and gbar (BUF_IN2).  A
+  // periodic seam is an ordinary merge here; a Neumann closure box has no
+  // beta, and its w-step read psi, so psibar = X^T wbar goes to fbar at the
+  // Neumann entries (in the reverse of the upward pass)
   H->adj_down_prog.clear();
   H->adj_up_prog.clear();
-  if (!pl.general_bc) {
+  {
     auto &P = H->adj_down_prog;
     P.clear();
     std::vector<ApplyDesc> t1, t2;
@@ -1068,13 +1070,17 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       std::vector<ApplyDesc> a2, a3;
       for (int b : lev) {
         const Box &B = pl.boxes[b];
-        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+        const bool clo = B.kind == 3;
+        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[clo ? B.alpha : B.beta];
         const int m = (int)B.gi.size();
-        const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+        const int ea = (int)A.fin.size(), eb = clo ? m : (int)C.fin.size();
         const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
         // wbar = ubar at the interior edge, summed over both children
-        v1.push_back(vop(m, vref(BUF_VEC, Lo.wb[b], -1, kInterleaved), vref(BUF_VEC, Lo.Ub[B.alpha] + n1, -1, kInterleaved),
-                         1.0, vref(BUF_VEC, Lo.Ub[B.beta] + n2, -1, kInterleaved), 1.0));
+        VecOpDesc wv = vop(m, vref(BUF_VEC, Lo.wb[b], -1, kInterleaved),
+                           vref(BUF_VEC, Lo.Ub[B.alpha] + n1, -1, kInterleaved), 1.0,
+                           vref(BUF_VEC, clo ? 0 : Lo.Ub[B.beta] + n2, -1, kInterleaved), 1.0);
+        if (clo) wv.b.buf = -1;          // the closure's outside sibling holds no unknowns
+        v1.push_back(wv);
         for (int part = 0; part < 2; ++part) {
           const int M = part == 0 ? n1 : n2;
           if (M == 0) continue;
@@ -1097,8 +1103,10 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       apply_step_t(a2, P);
       apply_step_t(a3, P);
     }
-    // fbar at the canonical boundary nodes from the roots' boundary slots
-    std::vector<int32_t> fmap(pl.bdry.size());
+    // fbar at the Dirichlet entries from the top boxes' boundary slots; zero
+    // at periodic entries (their data is not used); Neumann entries are
+    // written by the reverse of the upward pass
+    std::vector<int32_t> fpos, fmap, zpos;
     {
       std::unordered_map<int64_t, int64_t> where;
       for (int b = 0; b < nb; ++b) {
@@ -1106,16 +1114,37 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
         if (B.parent >= 0) continue;
         for (size_t k = 0; k < B.fin.size(); ++k) where[B.fin[k]] = Lo.Ub[b] + (int64_t)k;
       }
-      for (size_t k = 0; k < pl.bdry.size(); ++k) fmap[k] = (int32_t)where[pl.bdry[k]];
+      for (size_t k = 0; k < pl.bdry.size(); ++k) {
+        if (pl.bdry_kind[k] == kBcDirichlet) {
+          auto it = where.find(pl.bdry[k]);
+          if (it == where.end()) return fail(HPS_ETREE, "Dirichlet node missing from the top box");
+          fpos.push_back((int32_t)k);
+          fmap.push_back((int32_t)it->second);
+        } else if (pl.bdry_kind[k] == kBcPeriodic) {
+          zpos.push_back((int32_t)k);
+        }
+      }
     }
-    H->map_fbar = imap_put(fmap);
-    std::vector<VecOpDesc> fv{vop((int)pl.bdry.size(), vref(BUF_IN1, 0, -1, H->n_bdry),
-                                  vref(BUF_VEC, 0, H->map_fbar, kInterleaved), 1.0, vref(-1, 0, -1, 0), 0.0)};
-    fv[0].b.buf = -1;
+    std::vector<VecOpDesc> fv;
+    if (!fpos.empty()) {
+      H->map_fbar = imap_put(fmap);
+      const int64_t mpos = imap_put(fpos);
+      VecOpDesc v = vop((int)fpos.size(), vref(BUF_IN1, 0, mpos, H->n_bdry),
+                        vref(BUF_VEC, 0, H->map_fbar, kInterleaved), 1.0, vref(-1, 0, -1, 0), 0.0);
+      v.b.buf = -1;
+      fv.push_back(v);
+    }
+    if (!zpos.empty()) {
+      VecOpDesc v = vop((int)zpos.size(), vref(BUF_IN1, 0, imap_put(zpos), H->n_bdry),
+                        vref(-1, 0, -1, 0), 0.0, vref(-1, 0, -1, 0), 0.0);
+      v.a.buf = -1;
+      v.b.buf = -1;
+      fv.push_back(v);
+    }
     vecop_step(fv, P);
   }
   // adjoint, reverse of the upward pass (parents before children)
-  if (!pl.general_bc) {
+  {
     auto &P = H->adj_up_prog;
     P.clear();
     for (int h = pl.max_height; h >= 1; --h) {
@@ -1127,9 +1156,10 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       std::vector<VecOpDesc> u5;
       for (int b : lev) {
         const Box &B = pl.boxes[b];
-        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[B.beta];
+        const bool clo = B.kind == 3;
+        const Box &A = pl.boxes[B.alpha], &C = pl.boxes[clo ? B.alpha : B.beta];
         const int m = (int)B.gi.size();
-        const int ea = (int)A.fin.size(), eb = (int)C.fin.size();
+        const int ea = (int)A.fin.size(), eb = clo ? m : (int)C.fin.size();
         const int n1 = ea - m, n2 = eb - m, en = n1 + n2, ef = (int)B.fin.size();
         const bool root = B.parent < 0;
         // hbar in natural order: P_down^T hbar, or hbar through the permutation
@@ -1164,7 +1194,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
           a.B1 = vref(BUF_VEC, Lo.wb[b], -1, kInterleaved);
           a.alpha = side == 0 ? -1.0 : 1.0;
           a.C = side == 0 ? vref(BUF_VEC, Lo.hb[B.alpha] + n1, -1, kInterleaved)
-                          : vref(BUF_VEC, Lo.hb[B.beta] + n2, -1, kInterleaved);
+                          : clo ? vref(BUF_IN1, 0, Lo.map_psi[b], H->n_bdry)   // psibar
+                                : vref(BUF_VEC, Lo.hb[B.beta] + n2, -1, kInterleaved);
           u4.push_back(a);
         }
         for (int side = 0; side < 2; ++side) {       // kept parts pass through

@@ -112,7 +112,6 @@ extern "C" int hps_solve_adjoint(hps_handle *h, const double *ubar, int nrhs, do
   if (!h || !ubar || !fbar || !gbar) return fail(HPS_EINVAL, "NULL argument");
   if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
   if (h->econ) return fail(HPS_EINVAL, "the adjoint needs the stored leaf operators F");
-  if (h->pl.general_bc) return fail(HPS_EINVAL, "the adjoint is available for Dirichlet problems");
   hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
   int rc = ensure_solve_buffers(h, nrhs);
   if (rc) return rc;

@@ -174,9 +174,6 @@ def test_side_condition_refusals():
         H.Solver(t, coeffs, p, p - 1)
     with pytest.raises(H.HPSError, match="Dirichlet sides"):
         H.Solver(t, coeffs, p, p - 2, translation_invariant=True)
-    s = H.Solver(t, coeffs, p, p - 2, keep_fp32=True)
-    with pytest.raises(H.HPSError, match="Dirichlet problems"):
-        s.solve_adjoint(to_dev(np.zeros((1, t.n_leaves, p * p))))
     with pytest.raises(H.HPSError, match="opposite pairs"):
         H.Tree(0, 1, 0, 1, 4, 4).set_bc("PDDD")
     # a Dirichlet side allows q = p - 1
@@ -242,6 +239,47 @@ def test_crank_nicolson_mixed_precision():
     err = relerr(umx.cpu().numpy(), u64.cpu().numpy())
     print(f"CN mixed vs FP64 after {steps} steps: {err:.2e}", flush=True)
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("bc,nx,ny,p,q,refine", [
+    ("NPNP", 4, 4, 12, 10, None), ("PPPP", 4, 4, 12, 10, None),
+    ("NNNN", 4, 6, 10, 8, (0, 0.4, 0.55, 2)), ("DNDN", 4, 4, 16, 15, None),
+    ("NPDP", 4, 4, 12, 11, None)])
+def test_adjoint_with_side_conditions(bc, nx, ny, p, q, refine):
+    """The transposed sweeps against the forward solve: the dot-product
+    identity <u(f, g), ubar> = <f, fbar> + <g, gbar> on seeded random
+    vectors (f only on Dirichlet and Neumann entries, since periodic entries
+    are not read), for 3 right-hand sides; fbar is zero on periodic entries."""
+    import torch
+    H = _lib()
+    print(f"adjoint {bc} {nx}x{ny} p={p} q={q} refine={refine}", flush=True)
+    t = H.Tree(0, 1, 0, 1, nx, ny).set_bc(bc)
+    if refine:
+        t.refine_point(*refine)
+    xy = t.leaf_cheb_nodes(p)
+    coeffs = np.stack([W.varcoeff(xy[i, :, 0], xy[i, :, 1]) for i in range(len(xy))])
+    s = H.Solver(t, to_dev(coeffs), p, q)
+    rng = np.random.default_rng(17)
+    nrhs, nl, mi = 3, t.n_leaves, (p - 2) ** 2
+    b = t.bdry_gauss_nodes(q)
+    per = _kinds(b, bc) == "P"
+    f = rng.standard_normal((nrhs, s.n_bdry))
+    f[:, per] = 0.0
+    g = rng.standard_normal((nrhs, nl, mi))
+    ub = rng.standard_normal((nrhs, nl, p * p))
+    u = s.solve(to_dev(f), to_dev(g)).cpu().numpy()
+    fb, gb = s.solve_adjoint(to_dev(ub))
+    torch.cuda.synchronize()
+    fb, gb = fb.cpu().numpy(), gb.cpu().numpy()
+    for r in range(nrhs):
+        lhs = float(np.sum(u[r] * ub[r]))
+        rhs = float(np.sum(f[r] * fb[r]) + np.sum(g[r] * gb[r]))
+        scale = float(np.abs(u[r] * ub[r]).sum())
+        print(f"  rhs {r}: <u, ubar> {lhs:.12e}  <f, fbar> + <g, gbar> {rhs:.12e}", flush=True)
+        assert abs(lhs - rhs) <= 1e-12 * scale
+    assert np.all(fb[:, per] == 0.0)
+    if (~per).any():
+        assert np.abs(fb[:, ~per]).max() > 0.0
 
 
 def test_apply_operator_matches_oracle():
