@@ -133,10 +133,11 @@ int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
  * direction needs at least 4 leaves and no refined leaf on its sides; a
  * problem with a Neumann side needs at least 2 leaves; a problem without a
  * Dirichlet side needs q <= p - 2 (with q = p - 1 its discrete system is
- * singular).  Trees with a non-Dirichlet side have no translation_invariant
- * build; HPS_PREC_MIXED refines against the residual's flux rows at the
- * periodic seams and the Neumann nodes too, and hps_solve_adjoint returns
- * fbar = d/dpsi at Neumann entries and 0 at periodic entries.
+ * singular).  HPS_PREC_MIXED refines against the residual's flux rows at
+ * the periodic seams and the Neumann nodes too, and hps_solve_adjoint
+ * returns fbar = d/dpsi at Neumann entries and 0 at periodic entries.  A
+ * translation_invariant build keys a seam-closing merge by its two shared
+ * blocks and a closure by its root, so both get their own operators.
  * Errors: HPS_EINVAL (unknown code, unpaired periodic side, bad problem). */
 enum { HPS_BC_DIRICHLET = 0, HPS_BC_NEUMANN = 1, HPS_BC_PERIODIC = 2 };
 int hps_tree_set_bc(hps_tree *tree, int problem, const int *bc);

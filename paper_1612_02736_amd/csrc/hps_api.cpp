@@ -374,8 +374,6 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   // identical operators, stored once at the key's first box (rep).
   std::vector<int> rep(nb);
   for (int b = 0; b < nb; ++b) rep[b] = b;
-  if (H->dedup && pl.general_bc)
-    return fail(HPS_EINVAL, "translation_invariant builds need Dirichlet sides");
   if (H->dedup) {
     std::map<std::vector<int64_t>, int> first;
     std::vector<int64_t> kid(nb, -1);
@@ -384,6 +382,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       std::vector<int64_t> k;
       if (B.leaf) {
         k = {0, pl.leaf_class[B.leaf_index], B.role};
+      } else if (B.kind == 3) {        // Neumann closure: its root and its size
+        k = {3, kid[B.alpha], (int64_t)B.gi.size()};
       } else {
         k = {1, kid[B.alpha], kid[B.beta], B.cut, B.role, B.n_shared, (int64_t)B.gi.size()};
         k.insert(k.end(), B.pi.begin(), B.pi.end());
@@ -1478,8 +1478,6 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
     return fail(HPS_EINVAL, "economic and translation_invariant builds do not combine");
   int rc = plan_tree(H->tree, H->pl, q);
   if (rc) return rc;
-  if (H->dedup && H->pl.general_bc)
-    return fail(HPS_EINVAL, "translation_invariant builds need Dirichlet sides");
   H->p = p; H->q = q; H->mi = (p - 2) * (p - 2); H->me = 4 * (p - 1); H->g4 = 4 * q;
   H->nleaf = (int)H->pl.leaves.size();
   for (const Problem &P : H->tree.probs) {

@@ -172,8 +172,6 @@ def test_side_condition_refusals():
     coeffs = to_dev(np.stack([W.varcoeff(xy[i, :, 0], xy[i, :, 1]) for i in range(len(xy))]))
     with pytest.raises(H.HPSError, match="q <= p - 2"):
         H.Solver(t, coeffs, p, p - 1)
-    with pytest.raises(H.HPSError, match="Dirichlet sides"):
-        H.Solver(t, coeffs, p, p - 2, translation_invariant=True)
     with pytest.raises(H.HPSError, match="opposite pairs"):
         H.Tree(0, 1, 0, 1, 4, 4).set_bc("PDDD")
     # a Dirichlet side allows q = p - 1
@@ -280,6 +278,38 @@ def test_adjoint_with_side_conditions(bc, nx, ny, p, q, refine):
     assert np.all(fb[:, per] == 0.0)
     if (~per).any():
         assert np.abs(fb[:, ~per]).max() > 0.0
+
+
+@pytest.mark.parametrize("bc,n", [("NPNP", 16), ("PPPP", 8), ("NNNN", 8), ("PDPD", 8)])
+def test_translation_invariant_with_side_conditions(bc, n):
+    """Constant coefficients (the Crank-Nicolson operator of Sec. 7.6): the
+    build that stores one operator copy per distinct box solves exactly like
+    the full build (FP64 and mixed), with far less operator memory."""
+    import torch
+    H = _lib()
+    p, q, k = 16, 14, 0.01
+    t = H.Tree(0, 1, 0, 1, n, n).set_bc(bc)
+    xy = t.leaf_cheb_nodes(p)
+    X, Y = xy[..., 0], xy[..., 1]
+    cd = to_dev(np.stack([W.convdiff_coeffs(X[i], Y[i], k) for i in range(len(xy))]))
+    full = H.Solver(t, cd, p, q, keep_fp32=True)
+    shared = H.Solver(t, cd, p, q, keep_fp32=True, translation_invariant=True)
+    rng = np.random.default_rng(23)
+    f = to_dev(rng.standard_normal((4, full.n_bdry)))
+    g = to_dev(rng.standard_normal((4, t.n_leaves, (p - 2) ** 2)))
+    u1, u2 = full.solve(f, g), shared.solve(f, g)
+    m1 = full.solve(f, g, precision=H.HPS_PREC_MIXED)
+    m2 = shared.solve(f, g, precision=H.HPS_PREC_MIXED)
+    torch.cuda.synchronize()
+    d64 = relerr(u2.cpu().numpy(), u1.cpu().numpy())
+    dmx = relerr(m2.cpu().numpy(), u1.cpu().numpy())
+    wf = t.workspace_bytes(p, q)
+    ws = t.workspace_bytes(p, q, translation_invariant=True)
+    print(f"{bc} {n}x{n}: shared vs full {d64:.2e} (mixed {dmx:.2e}), operators {ws / wf:.3f} of full",
+          flush=True)
+    assert d64 <= 1e-13
+    assert dmx <= 1e-10
+    assert ws < 0.5 * wf
 
 
 def test_apply_operator_matches_oracle():
