@@ -5,8 +5,10 @@ The solver lives in the HIP/C++ library ``libhps.so`` (C ABI in
 solve and its adjoint as a ``torch.autograd.Function``.
 """
 
-from .hps import (HPS_PREC_FP32, HPS_PREC_FP64, HPS_PREC_MIXED, EXPORTS, HPSError,
-                  LIB_PATH, Solver, Tree, lib)
+from .hps import (HPS_BC_DIRICHLET, HPS_BC_NEUMANN, HPS_BC_PERIODIC, HPS_PREC_FP32,
+                  HPS_PREC_FP64, HPS_PREC_MIXED, EXPORTS, HPSError, LIB_PATH, Solver, Tree,
+                  lib)
 
 __all__ = ["Tree", "Solver", "HPSError", "lib", "LIB_PATH", "EXPORTS",
-           "HPS_PREC_FP64", "HPS_PREC_MIXED", "HPS_PREC_FP32"]
+           "HPS_PREC_FP64", "HPS_PREC_MIXED", "HPS_PREC_FP32",
+           "HPS_BC_DIRICHLET", "HPS_BC_NEUMANN", "HPS_BC_PERIODIC"]
