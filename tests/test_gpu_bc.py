@@ -312,6 +312,65 @@ def test_translation_invariant_with_side_conditions(bc, n):
     assert ws < 0.5 * wf
 
 
+def test_refactor_with_side_conditions_matches_fresh_build():
+    """hps_refactor (the build replayed as a HIP graph) on a periodic /
+    Neumann tree, three times with alternating coefficients, each against a
+    fresh build of the same coefficients (bitwise)."""
+    import torch
+    H = _lib()
+    p, q = 12, 10
+    t = H.Tree(0, 1, 0, 1, 8, 8).set_bc("NPNP")
+    xy = t.leaf_cheb_nodes(p)
+    X, Y = xy[..., 0], xy[..., 1]
+    cs = [to_dev(np.stack([W.convdiff_coeffs(X[i], Y[i], k) for i in range(len(xy))]))
+          for k in (0.01, 0.002)]
+    rng = np.random.default_rng(29)
+    s = H.Solver(t, cs[0], p, q)
+    f = to_dev(rng.standard_normal((2, s.n_bdry)))
+    g = to_dev(rng.standard_normal((2, t.n_leaves, (p - 2) ** 2)))
+    for rep in range(3):
+        c = cs[(rep + 1) % 2]
+        s.refactor(c)
+        u = s.solve(f, g)
+        ref = H.Solver(t, c, p, q).solve(f, g)
+        torch.cuda.synchronize()
+        d = float((u - ref).abs().max())
+        print(f"  refactor {rep}: max diff vs fresh build {d:.1e}", flush=True)
+        assert d == 0.0
+
+
+def test_autograd_gradient_with_side_conditions():
+    """Loss sum(u^2) on a periodic / Neumann tree: the autograd gradient with
+    respect to c (adjoint sweeps) against central differences along three
+    seeded directions (h = 1e-4; the loss is smooth in c, so the O(h^2)
+    truncation is far below the 1e-6 relative bound)."""
+    import torch
+    from paper_1612_02736_amd.autograd import hps_solve
+    H = _lib()
+    p, q = 12, 10
+    t = H.Tree(0, 1, 0, 1, 4, 4).set_bc("NPNP")
+    xy = t.leaf_cheb_nodes(p)
+    coeffs = np.stack([W.varcoeff(xy[i, :, 0], xy[i, :, 1]) for i in range(len(xy))])
+    cd = to_dev(coeffs)
+    s = H.Solver(t, cd, p, q)
+    rng = np.random.default_rng(31)
+    f = to_dev(rng.standard_normal((1, s.n_bdry)))
+    g = to_dev(rng.standard_normal((1, t.n_leaves, (p - 2) ** 2)))
+    c = to_dev(coeffs[:, 5]).requires_grad_(True)
+    u = hps_solve(s, cd, c, g, f)
+    (u ** 2).sum().backward()
+    grad = c.grad.cpu().numpy()
+    for k in range(3):
+        d = np.random.default_rng(700 + k).standard_normal(grad.shape)
+        h = 1e-4
+        with torch.no_grad():
+            lp = float((hps_solve(s, cd, c.detach() + h * to_dev(d), g, f) ** 2).sum())
+            lm = float((hps_solve(s, cd, c.detach() - h * to_dev(d), g, f) ** 2).sum())
+        fd, an = (lp - lm) / (2 * h), float(np.sum(grad * d))
+        print(f"  direction {k}: fd {fd:.10e} adjoint {an:.10e}", flush=True)
+        assert abs(fd - an) <= 1e-6 * abs(an)
+
+
 def test_apply_operator_matches_oracle():
     """sigma u - A u at interior nodes on random leaf values, 3 right-hand
     sides, variable coefficients on a refined tree."""
