@@ -286,3 +286,20 @@ def convdiff_smooth_initial(x, y, beta=12.0, xhat=CD_XHAT):
     by = (np.exp(beta * (np.cos(np.pi * (y - xhat[1])) - 1.0)) +
           np.exp(beta * (np.cos(np.pi * (y + xhat[1])) - 1.0)))
     return bx * by
+
+
+# -- Sec. 7.3: concentrated load, kappa = 20, refinement toward the load -----
+CONC_KAPPA = 20.0
+CONC_ALPHA = 3000.0
+CONC_XHAT = (0.25, 0.75)      # a vertex of the 4 x 4 grid (one level of refinement: 28 leaves)
+
+
+def concentrated_coeffs(x, y, kappa=CONC_KAPPA):
+    """-Lap u - kappa^2 u."""
+    z = np.zeros_like(x)
+    o = np.ones_like(x)
+    return np.stack([o, z, o.copy(), z, z.copy(), np.full_like(x, -kappa * kappa)])
+
+
+def concentrated_load(x, y, alpha=CONC_ALPHA, xhat=CONC_XHAT):
+    return np.exp(-alpha * ((x - xhat[0]) ** 2 + (y - xhat[1]) ** 2))
