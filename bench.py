@@ -151,6 +151,43 @@ def translation_invariant_case(H, torch, dev, nrhs, reps=3):
     return out
 
 
+def scaling_sweep(H, torch, dev, sizes=(16, 32, 64, 128), reps=3):
+    """Build and solve time and operator memory against the number of
+    unknowns N = (p n)^2 (the speed and memory experiments of Sec. 7.1):
+    the variable-coefficient problem on n x n leaves, p = 16, q = 15, random
+    right-hand sides (timing only)."""
+    out = []
+    rng = np.random.default_rng(5)
+    for n in sizes:
+        t = H.Tree(0.0, 1.0, 0.0, 1.0, n, n)
+        coeffs, _, _ = make_inputs(t, 1)
+        cd = torch.from_numpy(coeffs).to(dev)
+        s = H.Solver(t, cd, P, Q)
+        s.refactor(cd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.refactor(cd)
+        torch.cuda.synchronize()
+        fac = (time.perf_counter() - t0) / reps
+        row = {"n": n, "N": (P * n) ** 2, "factor_ms": fac * 1e3,
+               "operator_bytes_per_unknown": t.workspace_bytes(P, Q) / (P * n) ** 2}
+        for nrhs in (1, 32):
+            f = torch.from_numpy(rng.standard_normal((nrhs, s.n_bdry))).to(dev)
+            g = torch.from_numpy(rng.standard_normal((nrhs, t.n_leaves, (P - 2) ** 2))).to(dev)
+            s.solve(f, g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s.solve(f, g)
+            torch.cuda.synchronize()
+            row[f"solve_ms_nrhs{nrhs}"] = (time.perf_counter() - t0) * 1e3 / reps
+        out.append(row)
+        del s, cd
+        torch.cuda.empty_cache()
+    return out
+
+
 def crank_nicolson_case(H, torch, dev, k=0.01, steps=50):
     """The parabolic problem of Sec. 7.6: u_t = eps Lap u - u_x on 16 x 16
     leaves, periodic in x, zero Neumann data in y, Crank-Nicolson with time
@@ -320,6 +357,7 @@ def main():
     # full build vs one operator copy per distinct box
     ti = translation_invariant_case(H, torch, dev, args.nrhs)
     cn = crank_nicolson_case(H, torch, dev)
+    sweep = scaling_sweep(H, torch, dev)
     # accuracy against stored oracle values (seed 2 = right-hand side 0)
     rel_err = rel_err_mixed = None
     ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
@@ -403,6 +441,7 @@ def main():
         "operator_gb_economic": ws_econ / 1e9,
         "translation_invariant_heat_128x128_p12": ti,
         "crank_nicolson_periodic_neumann_16x16_p16": cn,
+        "scaling_varcoeff_p16": sweep,
         "rel_err_vs_oracle": rel_err,
         "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
