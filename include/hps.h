@@ -133,7 +133,8 @@ int hps_tree_uniform(double x0, double x1, double y0, double y1, int nx,
  * direction needs at least 4 leaves and no refined leaf on its sides; a
  * problem with a Neumann side needs at least 2 leaves; a problem without a
  * Dirichlet side needs q <= p - 2 (with q = p - 1 its discrete system is
- * singular).  HPS_PREC_MIXED refines against the residual's flux rows at
+ * singular).  The tree rules fail with HPS_ETREE in the node queries and
+ * hps_build, the q rule with HPS_EINVAL in hps_build.  HPS_PREC_MIXED refines against the residual's flux rows at
  * the periodic seams and the Neumann nodes too, and hps_solve_adjoint
  * returns fbar = d/dpsi at Neumann entries and 0 at periodic entries.  A
  * translation_invariant build keys a seam-closing merge by its two shared
