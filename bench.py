@@ -88,12 +88,12 @@ def flop_model(H, solver):
 
 
 def cpu_baseline(nrhs):
-    """The oracle as it stands on the host, two ways: on one thread with a
-    32 x 32-leaf sample of the same p = 16 problem (1/4 of the leaves,
-    scaled by 4), and with the BLAS thread pool at its default on 16 x 16
-    leaves (scaled by 16).  The oracle's blocks (196 x 196 and smaller) are
-    too small for threaded BLAS, which makes the threaded run ~10x slower;
-    the reported value is the faster, one-thread run."""
+    """The oracle as it stands on the host, two ways: on one thread on the
+    full 64 x 64-leaf problem (factor + one solve; the step's 32 solves are
+    32 times the one), and with the BLAS thread pool at its default on a
+    16 x 16-leaf sample (scaled by 16).  The oracle's blocks (196 x 196 and
+    smaller) are too small for threaded BLAS, which makes the threaded run
+    ~10-20x slower; the reported value is the faster, one-thread run."""
     from threadpoolctl import threadpool_info, threadpool_limits
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import oracle
@@ -114,11 +114,12 @@ def cpu_baseline(nrhs):
         b, sv = (t1 - t0) * scale, (t2 - t1) * scale
         return {"value": nrhs / (b + nrhs * sv), "cores": int(threads),
                 "sample": (f"oracle build + 1 solve on {n}x{n} leaves of the same p=16 problem "
-                           f"({t1 - t0:.1f} s + {t2 - t1:.2f} s), scaled x{scale:.0f} to 64x64; "
-                           f"step = factor + {nrhs} solves"),
+                           f"({t1 - t0:.1f} s + {t2 - t1:.2f} s)"
+                           + (f", scaled x{scale:.0f} to 64x64" if scale != 1 else "")
+                           + f"; step = factor + {nrhs} solves"),
                 "factor_s_scaled": b, "solve_s_scaled": sv}
 
-    one = run(32, 1)
+    one = run(N_LEAF_SIDE, 1)
     many = run(16, None)
     out = {"value": one["value"], "unit": "solves/s", "cores": 1, "kind": "oracle",
            "sample": one["sample"], "factor_s_scaled": one["factor_s_scaled"],
