@@ -16,8 +16,13 @@ reported: factor time, solve-only throughput at nrhs 32 and 1, achieved
 TFLOP/s, relative error against stored oracle values, the roofline of the
 dominant kernel (from HIP events around its launches in eager, profiled
 steps of the same work that follow the timed steps: the timed steps replay
-the factorization as a HIP graph, which admits no per-kernel events)
-and the CPU oracle timed on a bounded sample.
+the factorization as a HIP graph, which admits no per-kernel events),
+the CPU oracle (the full problem on one host thread, and a sample with the
+BLAS thread pool at its default), and side workloads reported apart from
+the headline: mixed-precision and adjoint solves, the storage-economic
+build, the translation-invariant heat build, Crank-Nicolson steps of the
+periodic / Neumann convection-diffusion problem, and build / solve time and
+operator memory against N.
 """
 
 import argparse
