@@ -37,15 +37,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N_LEAF_SIDE, P, Q, NRHS = 64, 16, 15, 32
-# HBM bytes per launch of the dominant kernel class from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs (bench.py --traffic-probe), scaled by a 1 GiB copy, and the
-# SHA-256 prefix of the kernel source they were taken on: the figure is
-# reported only while that source is unchanged.
-MEASURED_TRAFFIC = {"kernels_sha256": "1476bc615c58510a",
-                    "bytes_per_launch": {"gemm[0]": 406299187.0, "gj_leaf[0]": 1836947289.0,
-                                         "apply[0]": 119232624.0}}
+# HBM bytes per launch of each kernel class from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs (bench.py --traffic-probe), scaled by what the counters read
+# for a 1 GiB copy, keyed by the kernel class, with the SHA-256 prefix of the
+# source files of that kernel when the counters were taken: a figure is
+# reported only while those sources are unchanged.
+KERNEL_SOURCES = {"gemm": ["kernels_gemm.hip", "kernel_util.hpp"],
+                  "gj_leaf": ["kernels_gj_leaf.hip", "gj_core.hpp", "kernel_util.hpp"],
+                  "gj_panel": ["kernels_gj_blocked.hip", "gj_core.hpp", "kernel_util.hpp"],
+                  "apply": ["kernels_mfma.hip", "kernels_apply.hip", "kernel_util.hpp"]}
+MEASURED_TRAFFIC = {}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector = FP64 matrix
+
+
+def kernel_source_sha(kind):
+    """SHA-256 prefix of the source files of one kernel class."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kind, []):
+        with open(os.path.join(ROOT, "paper_1612_02736_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def make_inputs(tree, nrhs, p=P, q=Q):
@@ -419,11 +432,9 @@ def main():
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    import hashlib
-    with open(os.path.join(ROOT, "paper_1612_02736_amd", "csrc", "kernels.hip"), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    if MEASURED_TRAFFIC["kernels_sha256"] == sha:
-        roof["traffic"] = MEASURED_TRAFFIC["bytes_per_launch"].get(f"{dom[0]}[{dom[1]}]")
+    meas = MEASURED_TRAFFIC.get(f"{dom[0]}[{dom[1]}]")
+    if meas and meas[0] == kernel_source_sha(dom[0]):
+        roof["traffic"] = meas[1]
     roof["kernel"] = f"{dom[0]}[{dom[1]}]"
     roof["avg_launch_ms"] = avg_ms
     out = {

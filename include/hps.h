@@ -97,9 +97,11 @@ enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
 typedef struct {
   int precision;         /* HPS_PREC_*; MIXED = FP32 sweeps + FP64 residual
                             iterative refinement */
-  double ir_tol;         /* MIXED: stop when max|du| <= ir_tol * max|u| (0 -> 1e-11;
+  double ir_tol;         /* MIXED: stop when max|du| <= ir_tol * max|u| (0 -> 1e-10;
                             an FP32 sweep shrinks the error by ~1e-6, so the
-                            result is then well inside 1e-10) */
+                            result is then well inside 1e-10); a solve that
+                            ends above it returns HPS_ENOCONV, one that meets
+                            a NaN or Inf returns HPS_ENONFINITE */
   int max_iter;          /* MIXED: refinement steps (0 -> 6) */
   void *stream;          /* hipStream_t; 0 -> null stream */
   double *u_gauss;       /* optional device out [nrhs][n_gauss] */

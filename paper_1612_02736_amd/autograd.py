@@ -6,7 +6,10 @@ recomputed in place) and Algorithm 2.  Backward: the library's transposed
 sweeps (hps_solve_adjoint) give gbar and fbar; only the collocated PDE rows
 depend on c, so cbar = -sum_r gbar_r * u_r on interior nodes and 0 on
 exterior nodes (hps_coeff_grad_c).  The stored operators are reused, nothing
-is refactored in the backward pass.
+is refactored in the backward pass -- unless the solver was refactored after
+this forward (another forward on the same solver, for example a loss with
+two coefficient fields): then its operators belong to other coefficients,
+and the backward refactors with the coefficients this forward used first.
 """
 
 import torch
@@ -17,18 +20,24 @@ class HPSSolve(torch.autograd.Function):
     def forward(ctx, solver, coeffs, c, g, f):
         """solver: a built Solver; coeffs [nl, 6, p^2] (slot 5 is replaced by
         c); c [nl, p^2]; g [nrhs, nl, (p-2)^2]; f [nrhs, n_bdry]."""
-        full = coeffs.clone()
-        full[:, 5, :] = c
-        solver.refactor(full.contiguous())
-        u = solver.solve(f.contiguous(), g.contiguous())
+        full = coeffs.detach().clone()
+        full[:, 5, :] = c.detach()
+        full = full.contiguous()
+        solver.refactor(full)
+        u = solver.solve(f.detach().contiguous(), g.detach().contiguous())
         ctx.solver = solver
-        ctx.save_for_backward(u)
+        ctx.version = solver.version
+        ctx.save_for_backward(u, full)
         return u
 
     @staticmethod
     def backward(ctx, ubar):
         solver = ctx.solver
-        (u,) = ctx.saved_tensors
+        u, full = ctx.saved_tensors
+        if solver.version != ctx.version:
+            # the operators were rebuilt for other coefficients since forward
+            solver.refactor(full)
+            ctx.version = solver.version
         fbar, gbar = solver.solve_adjoint(ubar.contiguous())
         cbar = None
         if ctx.needs_input_grad[2]:

@@ -14,7 +14,9 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SRC = ["hps_api.cpp", "solve_ext.cpp", "plan.cpp", "spectral.cpp"]
-DEV_SRC = ["kernels.hip", "kernels_ext.hip"]
+DEV_SRC = ["kernels_gj_leaf.hip", "kernels_gj_merge.hip", "kernels_gj_blocked.hip",
+           "kernels_gemm.hip", "kernels_mfma.hip", "kernels_apply.hip",
+           "kernels_ext.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
@@ -28,20 +30,25 @@ def _run(cmd):
         raise RuntimeError("build step failed: " + " ".join(cmd))
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
+    """Compile every source (in parallel, at most `jobs` at a time) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for s in HOST_SRC:
         o = os.path.join(BUILD, s.replace(".cpp", ".o"))
-        _run(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        cmds.append(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in DEV_SRC:
         src = os.path.join(CSRC, s)
         if not os.path.exists(src):
             continue
         o = os.path.join(BUILD, s.replace(".hip", ".o"))
-        _run(["hipcc"] + HIP_FLAGS + ["-c", src, "-o", o])
+        cmds.append(["hipcc"] + HIP_FLAGS + ["-c", src, "-o", o])
         objs.append(o)
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
     tmp = OUT + ".tmp"
     _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
          ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64"])

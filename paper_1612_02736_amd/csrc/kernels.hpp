@@ -1,4 +1,4 @@
-// Launchers of the HIP kernels (kernels.hip).  All launches are asynchronous
+// Launchers of the HIP kernels (kernels_*.hip).  All launches are asynchronous
 // on the given stream; descriptor arrays live in device memory.
 #pragma once
 #include <hip/hip_runtime.h>

@@ -123,9 +123,10 @@ __global__ __launch_bounds__(256) void accumulate_kernel(double *__restrict__ x,
   }
 }
 
-// out[0] = max |a|, out[1] = max |b| over n entries.  Non-negative doubles
-// order like their bit patterns, so each workgroup's maximum is merged with
-// an unsigned 64-bit atomic max; out must hold zeros on entry.
+// out[0] = max |a|, out[1] = max |b| over n entries, a NaN entry counting
+// as +inf (fmax would drop it).  Non-negative doubles order like their bit
+// patterns, so each workgroup's maximum is merged with an unsigned 64-bit
+// atomic max; out must hold zeros on entry.
 __global__ __launch_bounds__(256) void maxabs2_kernel(const double *__restrict__ a,
                                                       const double *__restrict__ b, int64_t n,
                                                       unsigned long long *__restrict__ out) {
@@ -133,8 +134,9 @@ __global__ __launch_bounds__(256) void maxabs2_kernel(const double *__restrict__
   double ma = 0.0, mb = 0.0;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
        e += int64_t(gridDim.x) * blockDim.x) {
-    ma = fmax(ma, fabs(a[e]));
-    mb = fmax(mb, fabs(b[e]));
+    const double va = fabs(a[e]), vb = fabs(b[e]);
+    ma = fmax(ma, va == va ? va : HUGE_VAL);
+    mb = fmax(mb, vb == vb ? vb : HUGE_VAL);
   }
   sa[threadIdx.x] = ma;
   sb[threadIdx.x] = mb;

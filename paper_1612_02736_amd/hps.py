@@ -214,14 +214,17 @@ class Solver:
         self._h = h
         self.device = coeffs.device
         self._torch = torch
+        # counts refactorizations, so holders of earlier operators can tell
+        self.version = 0
 
     def refactor(self, coeffs, stream=None):
         """Algorithm 1 again for new coefficients, reusing the device memory."""
         if tuple(coeffs.shape) != (self.n_leaves, 6, self.p * self.p):
             raise ValueError("coeffs has the wrong shape")
+        self.version += 1
         _check(lib().hps_refactor(self._h, _dev_ptr(coeffs, "coeffs"), _stream(stream)))
 
-    def solve(self, f, g, precision=HPS_PREC_FP64, ir_tol=1e-11, max_iter=0,
+    def solve(self, f, g, precision=HPS_PREC_FP64, ir_tol=1e-10, max_iter=0,
               u_gauss=False, stream=None, stats=None):
         """f: [nrhs, n_bdry], g: [nrhs, n_leaves, (p-2)^2] -> u [nrhs, n_leaves, p^2]."""
         torch = self._torch

@@ -191,3 +191,67 @@ def test_coefficient_gradient_matches_oracle():
     _, go = oracle.solve_adjoint(ops, ub[0])
     co = oracle.coeff_gradient(ops, uo, go)[:, 5]
     assert relerr(cb, co) <= 1e-10
+
+
+def test_mixed_precision_error_codes():
+    """A mixed solve fed a NaN in its boundary data returns HPS_ENONFINITE;
+    one that stops above its tolerance (one refinement step against an
+    unreachable ir_tol) returns HPS_ENOCONV."""
+    H = _H()
+    p, q, n = 12, 11, 4
+    print("mixed precision error codes", flush=True)
+    t = H.Tree(0, 1, 0, 1, n, n)
+    coeffs, f, g, _ = lib_inputs(t, p, q, W.varcoeff, W.FourierSolution(6))
+    s = H.Solver(t, to_dev(coeffs), p, q, keep_fp32=True)
+    fbad = f.copy()
+    fbad[3] = np.nan
+    with pytest.raises(H.HPSError) as e:
+        s.solve(to_dev(fbad[None]), to_dev(g[None]), precision=H.HPS_PREC_MIXED)
+    assert e.value.code == -4
+    gbad = g.copy()
+    gbad[1, 7] = np.inf
+    with pytest.raises(H.HPSError) as e:
+        s.solve(to_dev(f[None]), to_dev(gbad[None]), precision=H.HPS_PREC_MIXED)
+    assert e.value.code == -4
+    with pytest.raises(H.HPSError) as e:
+        s.solve(to_dev(f[None]), to_dev(g[None]), precision=H.HPS_PREC_MIXED, ir_tol=1e-300,
+                max_iter=1)
+    assert e.value.code == -5
+    # and the same handle still solves normally afterwards
+    u = s.solve(to_dev(f[None]), to_dev(g[None]), precision=H.HPS_PREC_MIXED)
+    assert np.isfinite(u.cpu().numpy()).all()
+
+
+def test_autograd_two_forwards_before_backward():
+    """Two forwards on one solver with different coefficient fields, then one
+    backward through both: the gradients equal those of two separate
+    forward/backward passes (the first term's backward must not use the
+    second forward's operators)."""
+    import torch
+    from paper_1612_02736_amd.autograd import hps_solve
+    H = _H()
+    p, q, n = 12, 11, 4
+    print("autograd two forwards", flush=True)
+    t = H.Tree(0, 1, 0, 1, n, n)
+    coeffs, f, g, _ = lib_inputs(t, p, q, W.varcoeff, W.FourierSolution(8))
+    cd = to_dev(coeffs)
+    s = H.Solver(t, cd, p, q)
+    rng = np.random.default_rng(21)
+    c1 = to_dev(coeffs[:, 5, :] * (1 + 0.2 * rng.standard_normal(coeffs[:, 5, :].shape)))
+    c2 = to_dev(coeffs[:, 5, :] * (1 + 0.2 * rng.standard_normal(coeffs[:, 5, :].shape)))
+    gd, fd = to_dev(g[None]), to_dev(f[None])
+
+    def grads(terms):
+        cs = [c.clone().requires_grad_(True) for c in (c1, c2)]
+        loss = 0.0
+        for k in terms:
+            loss = loss + (hps_solve(s, cd, cs[k], gd, fd) ** 2).sum()
+        loss.backward()
+        return [None if c.grad is None else c.grad.cpu().numpy() for c in cs]
+
+    both = grads([0, 1])
+    one = grads([0])[0]
+    two = grads([1])[1]
+    assert relerr(both[0], one) <= 1e-12
+    assert relerr(both[1], two) <= 1e-12
+    assert relerr(one, two) > 1e-3          # the two fields give different gradients
