@@ -28,12 +28,12 @@ from .spectral import (cheb_nodes, diff_matrix, gauss_nodes, interp_matrix,
 from .tree import Tree
 from .leaf import leaf_operators, leaf_geometry
 from .hps import build, solve, solve_adjoint, coeff_gradient
-from .dense import dense_solve, assemble_system, residual
+from .dense import dense_solve, dense_adjoint, assemble_system, residual
 from .timestep import operator_apply, crank_nicolson
 
 __all__ = [
     "cheb_nodes", "diff_matrix", "gauss_nodes", "interp_matrix", "bary_weights",
     "Tree", "leaf_operators", "leaf_geometry", "build", "solve",
-    "solve_adjoint", "coeff_gradient", "dense_solve", "assemble_system",
+    "solve_adjoint", "coeff_gradient", "dense_solve", "dense_adjoint", "assemble_system",
     "residual", "operator_apply", "crank_nicolson",
 ]

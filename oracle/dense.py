@@ -18,7 +18,9 @@ u_c on every leaf and the value at every interior "master" Gauss node.  Rows:
   by the leaves on the two sides and gets an ordinary E3 row.  Only
   Dirichlet nodes are known values.
 
-``dense_solve`` solves this system directly; ``residual`` evaluates b - K x.
+``dense_solve`` solves this system directly; ``dense_adjoint`` solves the
+transposed system for the cotangents of the data; ``residual`` evaluates
+b - K x.
 """
 
 import numpy as np
@@ -183,3 +185,30 @@ def residual(tree, coeffs, p, q, u_c, u, f, g):
     b = _rhs(lay, f, g)
     x = np.concatenate([np.asarray(u_c).ravel(), np.asarray(u)[lay["masters"]]])
     return b - K @ x, lay
+
+
+def dense_adjoint(tree, coeffs, p, q, ubar_c):
+    """Transpose of the map (f, g) -> u_c through the global system.
+
+    u_c is the first block of x = K^-1 b(f, g), and b depends on the data
+    linearly: g fills the PDE rows (E1) with coefficient +1, f enters the
+    interpolation rows (E2) through -L f and the Neumann flux rows with
+    coefficient +1.  So with lam = K^-T [ubar_c; 0], gbar = lam at the E1
+    rows and fbar collects lam over the rows that read each entry of f.
+    Periodic entries of f are read by no row, so their fbar is 0.
+    Returns (fbar [n_bdry], gbar [n_leaves, (p-2)^2])."""
+    K, lay = assemble_system(tree, coeffs, p, q)
+    y = np.zeros(lay["nunk"])
+    y[:lay["nl"] * lay["p2"]] = np.asarray(ubar_c).ravel()
+    # K^T lam = y with the rows of K scaled as in dense_solve: (S K)^T mu = y,
+    # lam = S mu
+    s = 1.0 / abs(K).max(axis=1).toarray().ravel()
+    Ks = (sp.diags(s) @ K).toarray()
+    lam = s * sla.solve(Ks.T, y)
+    gbar = lam[lay["e1_rows"]].copy()
+    fbar = np.zeros(len(lay["bdry"]))
+    for (r, k, wgt) in lay["e2_f"]:
+        fbar[k] += wgt * lam[r]
+    for (r, k) in lay["e3_f"]:
+        fbar[k] += lam[r]
+    return fbar, gbar

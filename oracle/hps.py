@@ -171,13 +171,28 @@ def solve(ops, f, g):
 def solve_adjoint(ops, ubar_c):
     """Transpose of (f, g) -> u_c.  ubar_c: [n_leaves, p*p].
 
-    Returns (fbar [n_bdry], gbar [n_leaves, (p-2)^2]).  Dirichlet problems
-    only.
+    Returns (fbar [n_bdry], gbar [n_leaves, (p-2)^2]).  The steps of
+    ``solve`` are taken in reverse order, each transposed:
+
+    * downward pass, children before parents: u_c = S u_ge + F g at a leaf
+      sends S^T ubar_c to the leaf's Gauss nodes and F^T ubar_c to gbar;
+      u_gi = S u_ge + w at a parent sends the cotangent of u_gi to w (wbar)
+      and S^T of it to the parent's boundary nodes; a slave node written as
+      P_up times the coarse values sends its cotangent back through P_up^T;
+    * Neumann closure of a root (u_N = T_NN^-1 (psi - h_N - T_ND u_D)):
+      y = T_NN^-T ubar_N goes to the Neumann data psi, -y to the root's h at
+      the Neumann positions, and -T_ND^T y to the Dirichlet nodes of the root;
+    * the boundary data: fbar = ubar at Dirichlet entries, the closure's y at
+      Neumann entries and 0 at periodic entries (the forward solve does not
+      read f there);
+    * upward pass, parents before children: h = [h1a; h2b] + Q w with
+      w = X (h3b - h3a) sends hbar through P_down^T, then wbar += Q^T hbar and
+      d = X^T wbar to h3a (minus) and h3b (plus); at a leaf, h = H g sends
+      H^T hbar to gbar.
     """
     tree, p, q = ops.tree, ops.p, ops.q
-    if any(P["bc"] != ("D", "D", "D", "D") for P in tree.problems):
-        raise NotImplementedError("the adjoint covers Dirichlet problems")
     node_xy, bdry = tree.gauss(q)
+    kind = tree.bdry_kind(q)
     boxes = tree.boxes
     N = node_xy.shape[0]
     mi = (p - 2) ** 2
@@ -205,9 +220,28 @@ def solve_adjoint(ops, ubar_c):
             ub_s = ubar[sl_ids].copy()
             ubar[sl_ids] = 0.0
             np.add.at(ubar, tau.ge, tau.Pup[slaves].T @ ub_s)
-    fbar = ubar[bdry].copy()
-    # reverse of the upward pass: parents before children
+    # reverse of the Neumann closures
+    fbar = np.zeros(len(bdry))
     hbar = {tau.id: None for tau in boxes}
+    if ops.closure:
+        neu_pos = {int(bdry[i]): i for i in np.where(kind == "N")[0]}
+        for r in tree.roots:
+            c = ops.closure.get(r.id)
+            if c is None:
+                continue
+            ge = np.array(r.ge)
+            nN, nD = ge[c["iN"]], ge[c["iD"]]
+            y = sla.lu_solve(c["lu"], ubar[nN], trans=1)
+            ubar[nN] = 0.0
+            for a, j in enumerate(nN):
+                fbar[neu_pos[int(j)]] += y[a]
+            np.add.at(ubar, nD, -(c["TND"].T @ y))
+            hr = np.zeros(len(r.ge))
+            hr[c["iN"]] = -y
+            hbar[r.id] = hr
+    dm = kind == "D"
+    fbar[dm] = ubar[bdry[dm]]
+    # reverse of the upward pass: parents before children
     for tau in boxes:
         o = ops.box[tau.id]
         hb = hbar[tau.id]

@@ -255,3 +255,32 @@ def test_autograd_two_forwards_before_backward():
     assert relerr(both[0], one) <= 1e-12
     assert relerr(both[1], two) <= 1e-12
     assert relerr(one, two) > 1e-3          # the two fields give different gradients
+
+
+@pytest.mark.parametrize("bc,n,p,q", [("DDDD", 4, 12, 11), ("NPNP", 4, 12, 10)])
+def test_operator_residual_rows_match_oracle_residual(bc, n, p, q):
+    """The PDE rows of the global system's residual, b - K x, for arbitrary
+    (non-solution) leaf values: g - A u_c on every leaf's interior nodes.  The
+    library evaluates -A u_c with hps_apply_operator (sigma = 0), the kernel
+    the mixed-precision refinement uses for these rows; the oracle takes them
+    from its assembled system (oracle.residual)."""
+    H = _H()
+    print(f"residual rows {bc} {n}x{n} p={p} q={q}", flush=True)
+    t = H.Tree(0, 1, 0, 1, n, n).set_bc(bc)
+    ot = oracle.Tree.uniform(0, 1, 0, 1, n, n)
+    ot.set_bc(bc)
+    xy = t.leaf_cheb_nodes(p)
+    coeffs = np.stack([W.varcoeff(xy[i, :, 0], xy[i, :, 1]) for i in range(len(xy))])
+    rng = np.random.default_rng(41)
+    uc = rng.standard_normal((t.n_leaves, p * p))
+    g = rng.standard_normal((t.n_leaves, (p - 2) ** 2))
+    s = H.Solver(t, to_dev(coeffs), p, q)
+    neg_au = s.apply_operator(to_dev(uc[None]), 0.0)[0].cpu().numpy()
+    nxy, bdry = ot.gauss(q)
+    u = rng.standard_normal(len(nxy))
+    f = rng.standard_normal(len(bdry))
+    r, lay = oracle.residual(ot, coeffs, p, q, uc, u, f, g)
+    want = r[lay["e1_rows"]]
+    err = relerr(g + neg_au, want)
+    print(f"  g - A u vs oracle residual rows: {err:.2e}", flush=True)
+    assert err <= 1e-12

@@ -134,11 +134,17 @@ def test_many_rhs_matrix_core_path(nrhs):
 
 def test_polynomial_reproduction_full_size_64x64():
     """A solution of tensor degree <= q-1 is reproduced to roundoff on any
-    tree for the full variable-coefficient operator.  Roundoff grows with the
-    conditioning: the oracle's own error on this check is 7.6e-14, 3.1e-13 and
-    1.5e-12 at 8x8, 16x16 and 32x32 leaves (about 4.5x per doubling), so the
-    FP64 floor at 64x64 is about 7e-12; the bound allows 7x that floor."""
+    tree for the full variable-coefficient operator.  The FP64 floor at this
+    size is measured, not extrapolated: the oracle's own error on the same
+    polynomial is stored by tests/golden/make_oracle_refs.py for both split
+    orders (5.1e-12).  The library's elimination order differs again
+    (Gauss-Jordan inverses with threshold pivoting, FMA contraction, its own
+    summation orders); the bound allows 4x the oracle's measured floor."""
+    import os
     H = _lib()
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden",
+                               "oracle_varcoeff_64x64_p16_seed2.npz"), allow_pickle=False)
+    floor = max(float(ref["poly_err_xfirst"]), float(ref["poly_err_yfirst"]))
     p, q = 16, 15
     t = H.Tree(0, 1, 0, 1, 64, 64)
     sol = W.PolySolution(21, 6)
@@ -146,7 +152,9 @@ def test_polynomial_reproduction_full_size_64x64():
     s = H.Solver(t, to_dev(coeffs), p, q)
     u = s.solve(to_dev(f[None]), to_dev(g[None]))[0].cpu().numpy()
     ex = sol.u(xy[..., 0], xy[..., 1])
-    assert relerr(u, ex) <= 5e-11
+    err = relerr(u, ex)
+    print(f"64x64 polynomial: library {err:.3e}, oracle floor {floor:.3e}", flush=True)
+    assert err <= 4.0 * floor
 
 
 def test_singular_and_nonfinite_inputs_are_reported():
@@ -167,7 +175,9 @@ def test_singular_and_nonfinite_inputs_are_reported():
 def test_full_size_workload2_against_stored_oracle():
     """64 x 64 leaves, p = 16, seeded Fourier solution (seed 2): FP64 and
     mixed-precision solves against oracle values written by
-    tests/golden/make_oracle_refs.py (every 64th leaf)."""
+    tests/golden/make_oracle_refs.py, element by element on 436 leaves: both
+    diagonals (every leaf row and column), the leaves bordering the two top
+    interfaces x = 1/2 and y = 1/2, and the west column."""
     import os
     H = _lib()
     ref = np.load(os.path.join(os.path.dirname(__file__), "golden",
@@ -177,9 +187,13 @@ def test_full_size_workload2_against_stored_oracle():
     coeffs, f, g, _ = lib_inputs(t, p, q, W.varcoeff, W.FourierSolution(2))
     s = H.Solver(t, to_dev(coeffs), p, q, keep_fp32=True)
     u = s.solve(to_dev(f[None]), to_dev(g[None]))[0].cpu().numpy()
-    assert relerr(u[ref["leaves"]], ref["u"]) <= TOL
+    assert len(ref["leaves"]) >= 400
+    err = relerr(u[ref["leaves"]], ref["u"])
     um = s.solve(to_dev(f[None]), to_dev(g[None]), precision=H.HPS_PREC_MIXED)[0].cpu().numpy()
-    assert relerr(um[ref["leaves"]], ref["u"]) <= 1e-10
+    err_m = relerr(um[ref["leaves"]], ref["u"])
+    print(f"64x64 vs stored oracle: FP64 {err:.3e}, mixed {err_m:.3e}", flush=True)
+    assert err <= TOL
+    assert err_m <= 1e-10
 
 
 def test_refactor_graph_replays_match_fresh_builds():

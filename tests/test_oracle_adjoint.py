@@ -78,3 +78,78 @@ def test_coefficient_gradient_finite_differences():
         fd = (loss(coeffs + h * d)[0] - loss(coeffs - h * d)[0]) / (2 * h)
         an = np.sum(cbar * d)
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(L0)), (s, fd, an)
+
+
+def _bc_setup(bc, nx, ny, p, q, refine=None, seed=4):
+    t = oracle.Tree.uniform(0, 1, 0, 1, nx, ny)
+    t.set_bc(bc)
+    if refine:
+        t.refine_point(0, *refine)
+    coeffs, _, _, _ = make_inputs(t, p, q, W.varcoeff, W.FourierSolution(seed))
+    return t, coeffs
+
+
+BC_CASES = [("NPNP", 4, 4, 8, 6, None), ("PPPP", 4, 4, 8, 6, None),
+            ("NNNN", 3, 4, 8, 6, None), ("DNDN", 4, 3, 8, 7, None),
+            ("NPDP", 4, 4, 8, 7, None), ("NDDD", 3, 3, 8, 7, (0.3, 0.6, 1))]
+
+
+@pytest.mark.parametrize("bc,nx,ny,p,q,refine", BC_CASES)
+def test_adjoint_with_side_conditions_matches_transposed_global_system(bc, nx, ny, p, q, refine):
+    """The reverse sweeps (Algorithm 2 transposed, with the Neumann closure
+    reversed) against the brute-force route: lam = K^-T [ubar; 0] through the
+    global collocation system, whose Neumann rows read the data and whose
+    periodic seams are ordinary flux-continuity rows."""
+    t, coeffs = _bc_setup(bc, nx, ny, p, q, refine)
+    ops = oracle.build(t, coeffs, p, q)
+    rng = np.random.default_rng(31)
+    y = rng.standard_normal((len(t.leaves), p * p))
+    fb, gb = oracle.solve_adjoint(ops, y)
+    fd, gd = oracle.dense_adjoint(t, coeffs, p, q, y)
+    scale_g, scale_f = np.abs(gd).max(), np.abs(fd).max()
+    assert np.abs(gb - gd).max() <= 1e-10 * scale_g, np.abs(gb - gd).max() / scale_g
+    assert np.abs(fb - fd).max() <= 1e-10 * scale_f, np.abs(fb - fd).max() / scale_f
+    kind = t.bdry_kind(q)
+    assert np.all(fb[kind == "P"] == 0.0)
+    if "N" in bc:
+        assert np.abs(fb[kind == "N"]).max() > 1e-3 * scale_f   # the Neumann data matters
+
+
+@pytest.mark.parametrize("bc,nx,ny,p,q,refine", BC_CASES)
+def test_adjoint_with_side_conditions_dot_product_identity(bc, nx, ny, p, q, refine):
+    """<u_c(f, g), y> = <f, fbar> + <g, gbar> for the oracle's forward solve
+    (Algorithm 2 with the closure), including random data on periodic
+    entries, which the forward solve ignores and fbar zeroes."""
+    t, coeffs = _bc_setup(bc, nx, ny, p, q, refine)
+    ops = oracle.build(t, coeffs, p, q)
+    rng = np.random.default_rng(32)
+    _, bdry = t.gauss(q)
+    f1 = rng.standard_normal(len(bdry))
+    g1 = rng.standard_normal((len(t.leaves), (p - 2) ** 2))
+    y = rng.standard_normal((len(t.leaves), p * p))
+    uc, _ = oracle.solve(ops, f1, g1)
+    fb, gb = oracle.solve_adjoint(ops, y)
+    lhs = np.sum(uc * y)
+    rhs = np.sum(f1 * fb) + np.sum(g1 * gb)
+    assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.abs(uc * y).sum()), (lhs, rhs)
+
+
+def test_adjoint_closure_sign_is_pinned():
+    """A planted mistake in the reversed Neumann closure (the cotangent sent
+    to the root's h with the wrong sign) breaks the dense-route agreement."""
+    import oracle.hps as OH
+    t, coeffs = _bc_setup("NNNN", 3, 3, 8, 6)
+    ops = oracle.build(t, coeffs, p=8, q=6)
+    y = np.random.default_rng(33).standard_normal((len(t.leaves), 64))
+    _, gd = oracle.dense_adjoint(t, coeffs, 8, 6, y)
+    orig = OH.sla.lu_solve
+
+    def wrong(lu, b, trans=0):
+        return -orig(lu, b, trans=trans) if trans == 1 else orig(lu, b, trans=trans)
+
+    OH.sla.lu_solve = wrong
+    try:
+        _, gw = oracle.solve_adjoint(ops, y)
+    finally:
+        OH.sla.lu_solve = orig
+    assert np.abs(gw - gd).max() > 1e-3 * np.abs(gd).max()
