@@ -216,6 +216,31 @@ size_t hps_build_workspace_size_opts(const hps_tree *tree, int p, int q, int eco
 int hps_solve(hps_handle *h, const double *f, const double *g, int nrhs,
               double *u, const hps_solve_opts *opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hps_solve
+ * with the same arguments and results, whose work vectors and split-K
+ * partials live in one fixed device array of the library
+ * (HPS_SOLVE_NOALLOC_MAX_BYTES per device, held by every device that loads
+ * the library until the process ends) instead of buffers the handle grows
+ * on demand.  No hipMalloc, hipFree or allocating library routine runs.
+ * The array's device address is looked up once per device, on the first
+ * call with that device current.
+ *  - precision: HPS_PREC_FP64 or HPS_PREC_FP32 only (HPS_EINVAL for MIXED);
+ *    stored builds only (HPS_EINVAL for an economic handle); iters_out and
+ *    resid_out, when given, receive 0.
+ *  - HPS_EINVAL, with the bytes needed in the message, when nrhs right-hand
+ *    sides need more work memory than the array holds (64 x 64 leaves,
+ *    p = 16: 34.5 MB per right-hand side, so up to 7 fit; 32 x 32 leaves:
+ *    7.6 MB, up to 35).
+ *  - Every call on one device shares that device's array: calls that
+ *    overlap on one device (other host threads, or other streams before
+ *    this call's stream has drained) race and give undefined results.  The
+ *    array keeps the last call's contents; every entry a solve reads it has
+ *    written first, so nothing needs clearing between calls. */
+#define HPS_SOLVE_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+int hps_solve_noalloc(hps_handle *h, const double *f, const double *g, int nrhs,
+                      double *u, const hps_solve_opts *opts);
+
 /* Transpose of the linear map (f, g) -> u_c of hps_solve (not in the
  * paper): given ubar [nrhs][n_leaves][p*p] (device) returns
  * fbar [nrhs][n_bdry] and gbar [nrhs][n_leaves][(p-2)^2] (device) by the

@@ -27,6 +27,10 @@ int hps_debug_gemm(int M, int N, int K, double alpha, const double *A, int lda,
  * Returns HPS_ESINGULAR / HPS_ENONFINITE like hps_build. */
 int hps_debug_invert(int n, int batch, const double *A, double *X, void *stream);
 
+/* Bytes of solve work memory (work vectors and split-K partials) that
+ * nrhs right-hand sides take on this handle; 0 for bad arguments. */
+size_t hps_debug_solve_work_bytes(const hps_handle *h, int nrhs);
+
 /* Number of boxes of a built handle and, per box (pre-order numbering,
  * parents before children): [is_leaf, leaf index or -1, parent, alpha, beta,
  * n_fin, n_nat, m] into host int32 out[n_boxes][8]. */

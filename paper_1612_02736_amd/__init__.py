@@ -6,9 +6,10 @@ solve and its adjoint as a ``torch.autograd.Function``.
 """
 
 from .hps import (HPS_BC_DIRICHLET, HPS_BC_NEUMANN, HPS_BC_PERIODIC, HPS_PREC_FP32,
-                  HPS_PREC_FP64, HPS_PREC_MIXED, EXPORTS, HPSError, LIB_PATH, Solver, Tree,
+                  HPS_PREC_FP64, HPS_PREC_MIXED, HPS_SOLVE_NOALLOC_MAX_BYTES, EXPORTS, HPSError, LIB_PATH, Solver, Tree,
                   lib)
+from . import hps
 
 __all__ = ["Tree", "Solver", "HPSError", "lib", "LIB_PATH", "EXPORTS",
-           "HPS_PREC_FP64", "HPS_PREC_MIXED", "HPS_PREC_FP32",
+           "HPS_PREC_FP64", "HPS_PREC_MIXED", "HPS_PREC_FP32", "HPS_SOLVE_NOALLOC_MAX_BYTES",
            "HPS_BC_DIRICHLET", "HPS_BC_NEUMANN", "HPS_BC_PERIODIC"]

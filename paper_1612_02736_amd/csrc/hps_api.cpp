@@ -1649,14 +1649,23 @@ int ensure_solve_buffers(hps_handle *H, int nrhs) {
   return HPS_OK;
 }
 
-// One pass of Algorithm 2 in precision prec (0 FP64, 1 FP32 operators).
-// f, g, u are device arrays in the canonical layouts; jump (optional) adds
-// a flux-jump source on interior Gauss nodes (the refinement correction).
-int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, double *u,
-                   int prec, const double *jump, hipStream_t st) {
-  int rc = ensure_solve_buffers(H, nrhs);
-  if (rc) return rc;
+// Doubles of per-solve work memory for nrhs right-hand sides: the work
+// vectors (BUF_VEC) followed by the split-K partials (BUF_SCR).
+int64_t solve_vec_elems(const hps_handle *H, int nrhs) { return H->vec_per_rhs * nrhs; }
+int64_t solve_work_elems(const hps_handle *H, int nrhs) {
+  return (H->vec_per_rhs + H->part_per_rhs) * nrhs + 64;
+}
+
+// One pass of Algorithm 2 in precision prec (0 FP64, 1 FP32 operators) on
+// the given work memory (vec: solve_vec_elems doubles, scr: the split-K
+// partials).  f, g, u are device arrays in the canonical layouts; jump
+// (optional) adds a flux-jump source on interior Gauss nodes (the refinement
+// correction).
+int hps_solve_pass_on(hps_handle *H, const double *f, const double *g, int nrhs, double *u,
+                      int prec, const double *jump, double *vec, double *scr, hipStream_t st) {
   Bases bs = make_bases(H);
+  bs.d[BUF_VEC] = vec;
+  bs.d[BUF_SCR] = scr;
   if (prec == 1) {
     if (!H->has_fp32) return fail(HPS_EINVAL, "handle was built without keep_fp32");
     bs.d[BUF_WS] = H->ws32.p;
@@ -1666,12 +1675,58 @@ int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, do
   bs.d[BUF_IN2] = (void *)u;
   bs.d[BUF_AUX] = (void *)jump;
   // with a flux-jump source the w-steps read it as their third operand
-  rc = run_prog(H, jump ? H->up_jump_prog : H->up_prog, bs, nrhs, prec, st);
+  int rc = run_prog(H, jump ? H->up_jump_prog : H->up_prog, bs, nrhs, prec, st);
   if (rc) return rc;
   HIPCHK(launch_copy_map(bs, vref(BUF_VEC, H->ug_off, H->map_bdry, kInterleaved),
                          vref(BUF_IN0, 0, -1, H->n_bdry), H->n_bdry, nrhs, st));
   return run_prog(H, H->down_prog, bs, nrhs, prec, st);
 }
+
+// The same on the handle's own work buffers (grown on demand).
+int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, double *u,
+                   int prec, const double *jump, hipStream_t st) {
+  int rc = ensure_solve_buffers(H, nrhs);
+  if (rc) return rc;
+  return hps_solve_pass_on(H, f, g, nrhs, u, prec, jump, H->vec.p, H->scr.p, st);
+}
+
+// hps_solve on caller-supplied work memory of `bytes` bytes (device): no
+// allocation.  FP64 and FP32 sweeps of stored (not economic) builds only.
+int hps_solve_on_scratch(hps_handle *h, const double *f, const double *g, int nrhs, double *u,
+                         const hps_solve_opts *opts, double *work, size_t bytes) {
+  if (!h || !f || !g || !u) return fail(HPS_EINVAL, "NULL argument");
+  if (!work) return fail(HPS_EHIP, "no device address for the solve work array");
+  if (nrhs <= 0) return fail(HPS_EINVAL, "nrhs must be positive");
+  const int prec = opts ? opts->precision : HPS_PREC_FP64;
+  if (prec != HPS_PREC_FP64 && prec != HPS_PREC_FP32)
+    return fail(HPS_EINVAL, "the allocation-free solve runs FP64 or FP32 sweeps only");
+  if (h->econ)
+    return fail(HPS_EINVAL, "the allocation-free solve needs stored leaf operators (not economic)");
+  if (h->prof_on)
+    return fail(HPS_EINVAL, "per-launch profiling creates events; switch it off first");
+  const size_t need = size_t(solve_work_elems(h, nrhs)) * sizeof(double);
+  if (need > bytes)
+    return fail(HPS_EINVAL, "the solve needs " + std::to_string(need) + " bytes of work memory for " +
+                                std::to_string(nrhs) + " right-hand sides; the fixed array holds " +
+                                std::to_string(bytes));
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  double *vec = work, *scr = work + solve_vec_elems(h, nrhs);
+  int rc = hps_solve_pass_on(h, f, g, nrhs, u, prec == HPS_PREC_FP32 ? 1 : 0, nullptr, vec, scr, st);
+  if (rc) return rc;
+  if (opts && opts->u_gauss) {
+    Bases bs = make_bases(h);
+    bs.d[BUF_VEC] = vec;
+    bs.d[BUF_IN0] = opts->u_gauss;
+    HIPCHK(launch_copy_map(bs, vref(BUF_IN0, 0, -1, h->pl.n_gauss),
+                           vref(BUF_VEC, h->ug_off, -1, kInterleaved), h->pl.n_gauss, nrhs, st));
+  }
+  if (opts && opts->iters_out) *opts->iters_out = 0;
+  if (opts && opts->resid_out) *opts->resid_out = 0.0;
+  HIPCHK(hipStreamSynchronize(st));
+  return HPS_OK;
+}
+
+int hps_set_error(int code, const char *msg) { return fail(code, msg); }
 
 extern "C" int hps_solve(hps_handle *h, const double *f, const double *g, int nrhs, double *u,
                          const hps_solve_opts *opts) {
@@ -1762,6 +1817,11 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
     if (info[b] < 0) return fail(HPS_ENONFINITE, "non-finite pivot in matrix " + std::to_string(b));
   }
   return HPS_OK;
+}
+
+extern "C" size_t hps_debug_solve_work_bytes(const hps_handle *h, int nrhs) {
+  if (!h || nrhs <= 0) return 0;
+  return size_t(solve_work_elems(h, nrhs)) * sizeof(double);
 }
 
 extern "C" int hps_debug_boxes(const hps_handle *h, int *n_boxes, int32_t *out) {

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhps.so")
 
 HPS_PREC_FP64, HPS_PREC_MIXED, HPS_PREC_FP32 = 0, 1, 2
+HPS_SOLVE_NOALLOC_MAX_BYTES = 256 << 20      # size of the fixed work array (hps.h)
 HPS_BC_DIRICHLET, HPS_BC_NEUMANN, HPS_BC_PERIODIC = 0, 1, 2
 _BC_CODES = {"D": HPS_BC_DIRICHLET, "N": HPS_BC_NEUMANN, "P": HPS_BC_PERIODIC}
 _ERRS = {-1: "HPS_EINVAL", -2: "HPS_ETREE", -3: "HPS_ESINGULAR",
@@ -25,6 +26,7 @@ EXPORTS = ["hps_tree_uniform", "hps_tree_refine_point", "hps_tree_set_bc", "hps_
            "hps_bdry_gauss_nodes", "hps_gauss_nodes", "hps_tree_free",
            "hps_build", "hps_refactor", "hps_build_workspace_size",
            "hps_build_workspace_size_econ", "hps_build_workspace_size_opts", "hps_solve",
+           "hps_solve_noalloc",
            "hps_solve_adjoint", "hps_coeff_grad_c", "hps_apply_operator",
            "hps_handle_free", "hps_last_error"]
 
@@ -87,6 +89,7 @@ def lib():
     L.hps_build_workspace_size_opts.argtypes = [vp, ip, ip, ip, ip]
     L.hps_build_workspace_size_opts.restype = ctypes.c_size_t
     L.hps_solve.argtypes = [vp, vp, vp, ip, vp, ctypes.POINTER(SolveOpts)]
+    L.hps_solve_noalloc.argtypes = [vp, vp, vp, ip, vp, ctypes.POINTER(SolveOpts)]
     L.hps_solve_adjoint.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(SolveOpts)]
     L.hps_coeff_grad_c.argtypes = [vp, vp, vp, ip, vp, vp]
     L.hps_apply_operator.argtypes = [vp, vp, ip, dp, vp, vp]
@@ -252,6 +255,21 @@ class Solver:
             stats["resid"] = res.value
         return (u, ug) if u_gauss else u
 
+    def solve_noalloc(self, f, g, u, precision=HPS_PREC_FP64, stream=None):
+        """hps_solve_noalloc: Algorithm 2 into the caller's u [nrhs, n_leaves, p^2],
+        with the library's fixed work array (no device allocation)."""
+        nrhs = f.shape[0]
+        if tuple(f.shape) != (nrhs, self.n_bdry):
+            raise ValueError("f has the wrong shape")
+        if tuple(g.shape) != (nrhs, self.n_leaves, (self.p - 2) ** 2):
+            raise ValueError("g has the wrong shape")
+        if tuple(u.shape) != (nrhs, self.n_leaves, self.p * self.p):
+            raise ValueError("u has the wrong shape")
+        o = SolveOpts(precision=precision, stream=_stream(stream))
+        _check(lib().hps_solve_noalloc(self._h, _dev_ptr(f, "f"), _dev_ptr(g, "g"), nrhs,
+                                       _dev_ptr(u, "u"), ctypes.byref(o)))
+        return u
+
     def solve_adjoint(self, ubar, stream=None):
         """ubar: [nrhs, n_leaves, p^2] -> (fbar [nrhs, n_bdry], gbar [nrhs, n_leaves, mi])."""
         torch = self._torch
@@ -299,6 +317,8 @@ def _debug_lib():
         vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.hps_debug_gemm.argtypes = [ip, ip, ip, dp, vp, ip, vp, ip, vp, ip, vp]
         L.hps_debug_invert.argtypes = [ip, ip, vp, vp, vp]
+        L.hps_debug_solve_work_bytes.argtypes = [vp, ip]
+        L.hps_debug_solve_work_bytes.restype = ctypes.c_size_t
         L.hps_debug_boxes.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
         L.hps_debug_box_nodes.argtypes = [vp, ip, ip, vp]
         L.hps_debug_box_op.argtypes = [vp, ip, ip, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -328,6 +348,11 @@ def debug_invert(A):
     X = torch.empty_like(Ad)
     _check(_debug_lib().hps_debug_invert(n, b, _dev_ptr(Ad, "A"), _dev_ptr(X, "X"), _stream(None)))
     return X.transpose(1, 2)
+
+
+def debug_solve_work_bytes(solver, nrhs):
+    """Bytes of solve work memory nrhs right-hand sides take on this handle."""
+    return int(_debug_lib().hps_debug_solve_work_bytes(solver._h, nrhs))
 
 
 def debug_boxes(solver):
