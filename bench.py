@@ -140,6 +140,7 @@ def cpu_baseline(nrhs):
     one = run(N_LEAF_SIDE, 1)
     many = run(16, None)
     out = {"value": one["value"], "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "host_cpu_count": os.cpu_count(),
            "sample": one["sample"], "factor_s_scaled": one["factor_s_scaled"],
            "solve_s_scaled": one["solve_s_scaled"], "default_threads": many}
     return out
@@ -277,6 +278,196 @@ def crank_nicolson_case(H, torch, dev, k=0.01, steps=50):
     return out
 
 
+def heat_stepping_case(H, torch, dev, ntraj=32, nsteps=8):
+    """Backward-Euler heat stepping (I - dt Lap) u_{n+1} = u_n, dt = 1e-3, on
+    128 x 128 leaves, p = 12, q = 11, f = 0: one factorization, then 32
+    trajectories (seeded Gaussian-bump initial values, seeds 0..31) advanced
+    8 steps each, every step one solve of the batch of 32 right-hand sides
+    (256 solves), in FP64 and in mixed precision (FP32 sweeps refined in
+    FP64 to 1e-10).  The next right-hand side is the interior of the last
+    solution (a device gather between the solves, inside the timing)."""
+    import workloads as W
+    n, p, q = 128, 12, 11
+    t = H.Tree(0.0, 1.0, 0.0, 1.0, n, n)
+    xy = t.leaf_cheb_nodes(p)
+    X, Y = xy[..., 0], xy[..., 1]
+    coeffs = np.stack([W.heat_coeffs(X[i], Y[i]) for i in range(t.n_leaves)])
+    cd = torch.from_numpy(coeffs).to(dev)
+    s = H.Solver(t, cd, p, q, keep_fp32=True)
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
+    s.refactor(cd)
+    torch.cuda.synchronize()
+    factor_ms = (time.perf_counter() - b0) * 1e3
+    pi = p - 2
+    inner = torch.tensor([(iy + 1) * p + ix + 1 for iy in range(pi) for ix in range(pi)],
+                         device=dev)
+    u0 = torch.from_numpy(np.stack([W.gaussian_bumps(X, Y, k) for k in range(ntraj)])).to(dev)
+    f = torch.zeros((ntraj, s.n_bdry), dtype=torch.float64, device=dev)
+    out = {"workload": f"heat, backward Euler dt=1e-3, {n}x{n} leaves, p={p}, q={q}, "
+                       f"{ntraj} trajectories x {nsteps} steps",
+           "factor_ms": factor_ms}
+    finals = {}
+    for name, prec in (("fp64", H.HPS_PREC_FP64), ("mixed", H.HPS_PREC_MIXED)):
+        u = u0
+        s.solve(f, u.index_select(2, inner).contiguous(), precision=prec)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = {}
+        for _ in range(nsteps):
+            u = s.solve(f, u.index_select(2, inner).contiguous(), precision=prec, stats=stats)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"solves_per_s_{name}"] = ntraj * nsteps / dt
+        out[f"ms_per_step_{name}"] = dt * 1e3 / nsteps
+        if name == "mixed":
+            out["mixed_refinement_steps"] = stats.get("iters")
+        finals[name] = u
+    out["rel_diff_mixed_vs_fp64_after_8_steps"] = float(
+        (finals["mixed"] - finals["fp64"]).abs().max() / finals["fp64"].abs().max())
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def refined_forest_case(H, torch, dev, reps=3):
+    """64 independent problems in one build: 4 x 4 base leaves refined 8
+    levels toward a seeded point (seed 100 + k), coefficients of the
+    variable-coefficient family with seeded phases, Gaussian load of width
+    1e-3, zero boundary data, p = 16, q = 14.  Build time, solve time for the
+    64 loads (one right-hand side covers every problem), and the error
+    against stored oracle values of problems 0 and 37."""
+    import workloads as W
+    nprob, p, q = 64, 16, 14
+    draws = [W.refined_problem(100 + k) for k in range(nprob)]
+    t = H.Tree(0, 1, 0, 1, 4, 4, nprob)
+    for k, (_, xh) in enumerate(draws):
+        t.refine_point(k, xh[0], xh[1], 8)
+    xy = t.leaf_cheb_nodes(p)
+    # leaves are in canonical (problem, y0, x0) order: problem k's leaves are
+    # the k-th contiguous run; its length follows from the per-problem counts
+    boxes = t.leaf_boxes()
+    starts = [0]
+    for i in range(1, t.n_leaves):
+        if boxes[i, 2] < boxes[i - 1, 2] - 1e-12 or (
+                boxes[i, 2] == boxes[i - 1, 2] and boxes[i, 0] < boxes[i - 1, 0]):
+            starts.append(i)
+    prob = np.zeros(t.n_leaves, dtype=int)
+    for k, st in enumerate(starts):
+        prob[st:] = k
+    coeffs = np.stack([W.varcoeff(xy[i, :, 0], xy[i, :, 1], draws[prob[i]][0])
+                       for i in range(len(xy))])
+    pi = p - 2
+    inner = np.array([(iy + 1) * p + ix + 1 for iy in range(pi) for ix in range(pi)])
+    g = np.stack([W.gaussian_load(xy[i, inner, 0], xy[i, inner, 1], draws[prob[i]][1])
+                  for i in range(len(xy))])
+    cd = torch.from_numpy(coeffs).to(dev)
+    fd = torch.zeros((1, t.counts(q)[1]), dtype=torch.float64, device=dev)
+    gd = torch.from_numpy(g[None]).to(dev)
+    s = H.Solver(t, cd, p, q)
+    s.refactor(cd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.refactor(cd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    u = s.solve(fd, gd)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        u = s.solve(fd, gd)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out = {"workload": f"{nprob} problems, 4x4 base leaves refined 8 levels, p={p}, q={q}",
+           "leaves": t.n_leaves, "leaves_per_problem_min": int(np.bincount(prob).min()),
+           "leaves_per_problem_max": int(np.bincount(prob).max()),
+           "build_s": (t1 - t0) / reps, "solve_ms": (t3 - t2) * 1e3 / reps,
+           "solves_per_s": reps / (t3 - t2), "problems_per_s": nprob * reps / (t3 - t2)}
+    ref = os.path.join(ROOT, "tests", "golden", "oracle_refined_forest_p16_q14.npz")
+    if os.path.exists(ref):
+        z = np.load(ref, allow_pickle=False)
+        uu = u[0].cpu().numpy()
+        errs = {}
+        for k in z["problems"]:
+            uo = z[f"u_problem{k}"]
+            mine = uu[prob == k]
+            errs[int(k)] = (float(np.max(np.abs(mine - uo)) / np.max(np.abs(uo)))
+                            if mine.shape == uo.shape else None)
+        out["rel_err_vs_oracle_sampled_problems"] = errs
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def gradient_case(H, torch, dev, reps=3):
+    """Loss sum (u - u_obs)^2 over 32 problems of 32 x 32 leaves, p = 16
+    (variable-coefficient family with seeded phases, u_obs from a perturbed
+    zeroth-order coefficient): forward (refactor with c, then solve) and
+    backward (transposed sweeps and the coefficient gradient) through the
+    torch.autograd.Function; the adjoint's cost over the forward cost."""
+    import workloads as W
+    from paper_1612_02736_amd.autograd import hps_solve
+    n, p, q, nprob = 32, 16, 15, 32
+    t = H.Tree(0, 1, 0, 1, n, n, nprob)
+    nl = t.n_leaves
+    per = nl // nprob
+    xy = t.leaf_cheb_nodes(p)
+    phases = [W.problem_phases(300 + k) for k in range(nprob)]
+    coeffs = np.stack([W.varcoeff(xy[i, :, 0], xy[i, :, 1], phases[i // per])
+                       for i in range(nl)])
+    pi = p - 2
+    inner = np.array([(iy + 1) * p + ix + 1 for iy in range(pi) for ix in range(pi)])
+    sol = W.FourierSolution(2)
+    g = np.stack([sol.g(xy[i, inner, 0], xy[i, inner, 1], coeffs[i][:, inner])
+                  for i in range(nl)])
+    b = t.bdry_gauss_nodes(q)
+    f = sol.u(b[:, 0], b[:, 1])
+    cd = torch.from_numpy(coeffs).to(dev)
+    s = H.Solver(t, cd, p, q)
+    pert = W.Perturbation(3)
+    c_obs = torch.from_numpy(coeffs[:, 5] * (1 + 0.1 * pert(xy[..., 0], xy[..., 1]))).to(dev)
+    fd = torch.from_numpy(f[None]).to(dev)
+    gd = torch.from_numpy(g[None]).to(dev)
+    with torch.no_grad():
+        u_obs = hps_solve(s, cd, c_obs, gd, fd)
+    fw = bw = 0.0
+    sol_ms = adj_ms = 0.0
+    for r in range(reps + 1):
+        c = cd[:, 5].clone().requires_grad_(True)
+        gv = gd.clone().requires_grad_(True)
+        fv = fd.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = hps_solve(s, cd, c, gv, fv)
+        L = ((u - u_obs) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        # the solve alone and the transposed sweeps alone, on the same handle
+        us = s.solve(fd, gd)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        s.solve_adjoint(2.0 * (us - u_obs))
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        if r:
+            fw += t1 - t0
+            bw += t2 - t1
+            sol_ms += (t3 - t2) * 1e3
+            adj_ms += (t4 - t3) * 1e3
+    out = {"workload": f"{nprob} problems x {n}x{n} leaves, p={p}, loss ||u - u_obs||^2",
+           "forward_ms": fw * 1e3 / reps, "backward_ms": bw * 1e3 / reps,
+           "backward_over_forward": bw / fw,
+           "solve_ms": sol_ms / reps, "adjoint_sweeps_ms": adj_ms / reps,
+           "adjoint_over_solve": adj_ms / sol_ms}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +475,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nrhs", type=int, default=NRHS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time build and solve against N (16x16 to 128x128 leaves)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one eager factor + solve and a 1 GiB device copy (for HBM "
                          "counter runs: the copy calibrates FETCH_SIZE / WRITE_SIZE); "
@@ -303,7 +496,7 @@ def main():
     cd = torch.from_numpy(coeffs).to(dev)
     fd = torch.from_numpy(f).to(dev)
     gd = torch.from_numpy(g).to(dev)
-    solver = H.Solver(tree, cd, P, Q, keep_fp32=True)
+    solver = H.Solver(tree, cd, P, Q)
     if args.traffic_probe:
         debug_profile(solver, True)        # eager launches, one dispatch per step
         solver.refactor(cd)
@@ -353,15 +546,33 @@ def main():
         solver.solve(f1, g1)
     torch.cuda.synchronize()
     solve1_ms = (time.perf_counter() - s0) * 1e2
-    # mixed precision (FP32 sweeps + FP64 residual refinement) at nrhs = 32
+    # mixed precision (FP32 sweeps + FP64 residual refinement) at nrhs = 32,
+    # on a handle that also keeps FP32 copies of the solve operators (their
+    # cast is timed on its own, outside the FP64 factorization)
+    sm = H.Solver(tree, cd, P, Q, keep_fp32=True)
+    sm.refactor(cd)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for _ in range(3):
+        sm.refactor(cd)
+    torch.cuda.synchronize()
+    factor_fp32_copies_ms = (time.perf_counter() - c0) * 1e3 / 3
     stats = {}
-    um = solver.solve(fd, gd, precision=H.HPS_PREC_MIXED, stats=stats)
+    um = sm.solve(fd, gd, precision=H.HPS_PREC_MIXED, stats=stats)
     torch.cuda.synchronize()
     m0 = time.perf_counter()
     for _ in range(3):
-        um = solver.solve(fd, gd, precision=H.HPS_PREC_MIXED, stats=stats)
+        um = sm.solve(fd, gd, precision=H.HPS_PREC_MIXED, stats=stats)
     torch.cuda.synchronize()
     mixed_ms = (time.perf_counter() - m0) * 1e3 / 3
+    u32 = sm.solve(fd, gd, precision=H.HPS_PREC_FP32)
+    torch.cuda.synchronize()
+    m1 = time.perf_counter()
+    for _ in range(3):
+        u32 = sm.solve(fd, gd, precision=H.HPS_PREC_FP32)
+    torch.cuda.synchronize()
+    fp32_sweep_ms = (time.perf_counter() - m1) * 1e3 / 3
+    del sm, u32
     # adjoint (transposed sweeps) at nrhs = 32
     ub = torch.ones_like(u)
     solver.solve_adjoint(ub)
@@ -388,7 +599,10 @@ def main():
     # full build vs one operator copy per distinct box
     ti = translation_invariant_case(H, torch, dev, args.nrhs)
     cn = crank_nicolson_case(H, torch, dev)
-    sweep = scaling_sweep(H, torch, dev)
+    sweep = scaling_sweep(H, torch, dev) if args.sweep else None
+    heat = heat_stepping_case(H, torch, dev)
+    forest = refined_forest_case(H, torch, dev)
+    grad = gradient_case(H, torch, dev)
     # accuracy against stored oracle values (seed 2 = right-hand side 0)
     rel_err = rel_err_mixed = None
     ref = os.path.join(ROOT, "tests", "golden", "oracle_varcoeff_64x64_p16_seed2.npz")
@@ -458,6 +672,8 @@ def main():
         "solves_per_s_fp64_nrhs1": 1e3 / solve1_ms,
         "solve_ms_mixed_nrhs32": mixed_ms,
         "solves_per_s_mixed_nrhs32": args.nrhs * 1e3 / mixed_ms,
+        "solve_ms_fp32_sweep_nrhs32": fp32_sweep_ms,
+        "factor_ms_with_fp32_copies": factor_fp32_copies_ms,
         "mixed_refinement_steps": stats.get("iters"),
         "mixed_last_correction": stats.get("resid"),
         "adjoint_ms_nrhs32": adj_ms,
@@ -470,13 +686,17 @@ def main():
         "operator_gb_economic": ws_econ / 1e9,
         "translation_invariant_heat_128x128_p12": ti,
         "crank_nicolson_periodic_neumann_16x16_p16": cn,
-        "scaling_varcoeff_p16": sweep,
+        "heat_backward_euler_128x128_p12": heat,
+        "refined_forest_64_problems_p16": forest,
+        "gradient_32_problems_32x32_p16": grad,
         "rel_err_vs_oracle": rel_err,
         "rel_err_mixed_vs_oracle": rel_err_mixed,
         "kernel_ms_per_step": {f"{k[0]}[{k[1]}]": v for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "kernel_rates": rates,
         "roofline": roof,
     }
+    if sweep is not None:
+        out["scaling_varcoeff_p16"] = sweep
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.nrhs)
     print(json.dumps(out))
