@@ -89,6 +89,17 @@ typedef struct {
                             leaf with the first leaf's on the device and
                             return HPS_EINVAL if any differ (bitwise); not
                             combined with economic. */
+  void *workspace;       /* optional caller-owned device memory for the FP64
+                            operators (for example a torch tensor), at least
+                            hps_build_workspace_size() bytes, 256-byte
+                            aligned; it also holds the reference matrices the
+                            build uploads once, so the caller leaves it
+                            untouched while the handle lives, and it must
+                            outlive the handle, which never frees it.  NULL:
+                            the library allocates the operator memory itself.
+                            Build scratch, solve work vectors and FP32 copies
+                            stay library-owned. */
+  size_t workspace_bytes; /* size of workspace (ignored when it is NULL) */
 } hps_build_opts;
 
 enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
@@ -97,16 +108,24 @@ enum { HPS_PREC_FP64 = 0, HPS_PREC_MIXED = 1, HPS_PREC_FP32 = 2 };
 typedef struct {
   int precision;         /* HPS_PREC_*; MIXED = FP32 sweeps + FP64 residual
                             iterative refinement */
-  double ir_tol;         /* MIXED: stop when max|du| <= ir_tol * max|u| (0 -> 1e-10;
-                            an FP32 sweep shrinks the error by ~1e-6, so the
-                            result is then well inside 1e-10); a solve that
-                            ends above it returns HPS_ENOCONV, one that meets
-                            a NaN or Inf returns HPS_ENONFINITE */
+  double ir_tol;         /* MIXED: relative error target (0 -> 1e-10).  Each
+                            FP32 sweep solves the correction equation to a
+                            relative accuracy rho (~1e-6), so after a
+                            correction du the remaining error is about
+                            rho max|du|; rho is estimated as the ratio of
+                            successive corrections (the first sweep's u
+                            counting as the first).  The refinement stops
+                            when max|du| <= ir_tol max|u|, or when
+                            rho <= 1e-3 and 100 rho max|du| <= ir_tol max|u|;
+                            a solve that ends above it returns HPS_ENOCONV,
+                            one that meets a NaN or Inf HPS_ENONFINITE */
   int max_iter;          /* MIXED: refinement steps (0 -> 6) */
   void *stream;          /* hipStream_t; 0 -> null stream */
   double *u_gauss;       /* optional device out [nrhs][n_gauss] */
   int *iters_out;        /* optional host out: refinement steps taken */
-  double *resid_out;     /* optional host out: last max|du|/max|u| */
+  double *resid_out;     /* optional host out: the estimated relative error
+                            at exit (the smaller of max|du|/max|u| and rho
+                            times it) */
 } hps_solve_opts;
 
 /* -- trees (host objects) ------------------------------------------------- */
@@ -152,24 +171,34 @@ int hps_tree_set_bc(hps_tree *tree, int problem, const int *bc);
 int hps_tree_refine_point(hps_tree *tree, int problem, double px, double py,
                           int n_ref, double t);
 
+/* Sizes of the tree of boxes (Sec. 2: the domain is split into a binary
+ * tree whose leaves carry the discretisation; Sec. 6.1 for refined trees):
+ * problems, leaves, boxes, merge levels and refinement depth. */
 int hps_tree_info(const hps_tree *tree, hps_tree_info_t *info);
 
-/* Number of Gauss nodes for a given q: all nodes, and those on the domain
- * boundary (the length of f per right-hand side). */
+/* Number of Gauss nodes for a given q (Sec. 2 and 3.1: q Gauss-Legendre
+ * nodes on each leaf side, shared by the two leaves of an interior side):
+ * all nodes, and those on the domain boundary (the length of f per
+ * right-hand side). */
 int hps_tree_counts(const hps_tree *tree, int q, int64_t *n_gauss,
                     int64_t *n_bdry);
 
-/* host out [n_leaves][p*p][2]: (x, y) of every leaf Chebyshev node. */
+/* host out [n_leaves][p*p][2]: (x, y) of every leaf Chebyshev node (the
+ * p x p tensor grid of Sec. 3.1 on each leaf, where the coefficients and g
+ * are sampled and u is returned). */
 int hps_leaf_cheb_nodes(const hps_tree *tree, int p, double *xy);
 
-/* host out [n_leaves][4]: x0, x1, y0, y1 of every leaf. */
+/* host out [n_leaves][4]: x0, x1, y0, y1 of every leaf (Sec. 2). */
 int hps_leaf_boxes(const hps_tree *tree, double *boxes);
 
-/* host out [n_bdry][2]: canonical boundary Gauss nodes (on a periodic side,
- * the seam nodes it shares with its partner, at the partner's coordinates). */
+/* host out [n_bdry][2]: canonical boundary Gauss nodes, where f is given
+ * (Sec. 3.1 places q Gauss nodes on every leaf side; on a periodic side these
+ * are the seam nodes it shares with its partner, at the partner's
+ * coordinates). */
 int hps_bdry_gauss_nodes(const hps_tree *tree, int q, double *xy);
 
-/* host out [n_gauss][2]: every Gauss node in the order of u_gauss. */
+/* host out [n_gauss][2]: every Gauss node in the order of u_gauss (the
+ * vector u of Gauss-node values of Sec. 3.1 and Algorithm 2). */
 int hps_gauss_nodes(const hps_tree *tree, int q, double *xy);
 
 void hps_tree_free(hps_tree *tree);
@@ -178,8 +207,11 @@ void hps_tree_free(hps_tree *tree);
 
 /* coeffs: device [n_leaves][6][p*p], nodal c11, c12, c22, c1, c2, c.
  * Builds F, S, H, T on every leaf (Sec. 3) and X, S, T on every merge
- * (Sec. 4), with P_up/P_down on refined interfaces (Sec. 6.3).  The handle
- * owns the operators (device memory) and keeps a copy of the tree.
+ * (Sec. 4), with P_up/P_down on refined interfaces (Sec. 6.3).  The
+ * operators live in opts->workspace when one is given (caller-owned) and in
+ * device memory of the handle otherwise; the handle keeps a copy of the
+ * tree.  A workspace smaller than hps_build_workspace_size() or not 256-byte
+ * aligned fails with HPS_EINVAL.
  * Errors: HPS_EINVAL (p < 4, q < 2, q >= p, NULL), HPS_ESINGULAR (message
  * names the first failing box), HPS_ENONFINITE, HPS_EHIP, HPS_ENOMEM.  On
  * failure *out is NULL. */
@@ -193,15 +225,14 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p,
  * a successful refactor. */
 int hps_refactor(hps_handle *h, const double *coeffs, void *stream);
 
-/* Device bytes the operators of a build take (FP64 only). */
-size_t hps_build_workspace_size(const hps_tree *tree, int p, int q);
-
-/* The same for a build with hps_build_opts.economic = economic. */
-size_t hps_build_workspace_size_econ(const hps_tree *tree, int p, int q, int economic);
-
-/* The same with hps_build_opts.economic and .translation_invariant. */
-size_t hps_build_workspace_size_opts(const hps_tree *tree, int p, int q, int economic,
-                                     int translation_invariant);
+/* Device bytes of the FP64 operators a build with these options stores
+ * (opts may be NULL; its q, economic and translation_invariant fields
+ * count): the size hps_build_opts.workspace must have.  Stored per leaf:
+ * [S_ci | F], H and T (Sec. 3, eqs. alpine3-alpine4; without F for an
+ * economic build, the storage-efficient version of Sec. 5.4), per merge X,
+ * S and T (Sec. 4), and the refinement tables P (Sec. 6.3).  0 for bad
+ * arguments. */
+size_t hps_build_workspace_size(const hps_tree *tree, int p, const hps_build_opts *opts);
 
 /* -- solve stage (Algorithm 2) -------------------------------------------- */
 

@@ -21,6 +21,13 @@ extern "C" {
 int hps_debug_gemm(int M, int N, int K, double alpha, const double *A, int lda,
                    const double *B, int ldb, double *C, int ldc, void *stream);
 
+/* The same on one tile variant of the kernel (0: 64 x 64, 1: 128 x 64,
+ * 2: 64 x 128, 3: 128 x 128, 4: 32 x 32, 5: 64 x 32, 6: 32 x 64 output tiles
+ * with K chunks of 16; 7: 64 x 64 with K chunks of 8); every variant must
+ * give bitwise the same C. */
+int hps_debug_gemm_variant(int variant, int M, int N, int K, double alpha, const double *A,
+                           int lda, const double *B, int ldb, double *C, int ldc, void *stream);
+
 /* X_i = inverse(A_i) for `batch` column-major n x n matrices stored one after
  * another (device), by the Gauss-Jordan kernel the build uses for an
  * interface block of size n (register-resident for n <= 196, blocked above).
@@ -46,12 +53,17 @@ int hps_debug_box_nodes(const hps_handle *h, int box, int which, int64_t *out);
  * 4q x (p-2)^2).  Returns the element count through *count. */
 int hps_debug_box_op(const hps_handle *h, int box, int which, double *out, int64_t *count);
 
+/* GEMM tile variant the tuner chose for each GEMM step of the build
+ * program, in program order, into host out[max_n]; *count receives the
+ * number of GEMM steps. */
+int hps_debug_gemm_choices(const hps_handle *h, int *out, int max_n, int *count);
+
 /* Per-launch timing: when enabled, every kernel launch step of builds and
  * solves on this handle is bracketed by HIP events on the caller's stream.
  * hps_debug_profile_read waits for the device, returns (kind, ms, work)
  * triples of the steps recorded since the last read (kind = 16 * step type +
  * variant, the variant being the size class of an interface Gauss-Jordan
- * and 0 otherwise; types 0 GEMM,
+ * (GEMM: its tile variant) and 0 otherwise; types 0 GEMM,
  * 1 leaf Gauss-Jordan, 2 interface Gauss-Jordan,
  * 3 interface difference, 4 panel, 5 column permutation, 6 solve apply) and
  * clears them.  work is the launch's algorithmic flop count (GEMM,

@@ -31,11 +31,13 @@ template <typename T>
 struct DevArray {
   T *p = nullptr;
   size_t n = 0;
+  bool owned = true;    // false: caller-owned memory (never freed here)
   ~DevArray() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     n = 0;
+    owned = true;
   }
   hipError_t alloc(size_t count) {
     reset();
@@ -43,6 +45,12 @@ struct DevArray {
     hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
     if (e == hipSuccess) n = count;
     return e;
+  }
+  void borrow(T *q, size_t count) {
+    reset();
+    p = q;
+    n = count;
+    owned = false;
   }
   hipError_t upload(const std::vector<T> &v) {
     hipError_t e = alloc(v.size());
@@ -67,6 +75,10 @@ struct Step {
   int64_t fin_maxm = 0;
   int64_t tmap0 = 0;          // GEMM / APPLY: start of the step's tile map
   bool trans = false;         // APPLY: transposed operator
+  // GEMM: tile variant in use (set by the tuner) and, per variant, the
+  // start of the step's tile map and its tile count
+  int var = 0;
+  int64_t vtmap0[8] = {}, vtiles[8] = {};
   // Algorithmic work of the launch: flops (GEMM, Gauss-Jordan, panel) or
   // operator elements read per right-hand side (APPLY).
   double work = 0.0;
@@ -96,8 +108,11 @@ struct hps_handle {
   hps::DevArray<int32_t> imap, info, ipiv, psrc;
   size_t solve_elems = 0;
   // descriptors
-  hps::DevArray<hps::GemmDesc> d_gemm;
-  hps::DevArray<int32_t> d_gemm_tmap, d_apply_tmap;   // tile -> descriptor (per step)
+  // GEMM descriptors and tile maps, one copy per tile variant (the
+  // descriptors differ only in their tiling fields)
+  hps::DevArray<hps::GemmDesc> d_gemm_v[8];
+  hps::DevArray<int32_t> d_gemm_tmap_v[8];
+  hps::DevArray<int32_t> d_apply_tmap;   // tile -> descriptor (per step)
   hps::DevArray<hps::LeafDesc> d_leaf;
   hps::DevArray<hps::MergeInvDesc> d_minv;
   hps::DevArray<hps::ApplyDesc> d_apply;
@@ -136,6 +151,7 @@ struct hps_handle {
   int64_t scr_build = 0;          // scratch doubles the build needs
   // optional per-step timing (test hook): events around every launch step
   bool prof_on = false;
+  bool tune_gemm = false;         // time the GEMM tile variants in the next build pass
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
   std::vector<double> prof_work;
   std::vector<hipEvent_t> prof_pool;

@@ -7,7 +7,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -34,11 +37,11 @@ struct GemmList {
   std::vector<GemmDesc> d;
   std::vector<int32_t> tmap;   // owning descriptor of each tile (index into d)
   int64_t tiles = 0;
-  void add(const GemmDesc &g0) {   // 64 x 64 tiles
+  void add(const GemmDesc &g0, int TM = 64, int TN = 64) {   // TM x TN tiles
     GemmDesc g = g0;
     if (g.M <= 0 || g.N <= 0) return;
-    g.tn = (g.N + 63) / 64;
-    const int64_t tm = (g.M + 63) / 64;
+    g.tn = (g.N + TN - 1) / TN;
+    const int64_t tm = (g.M + TM - 1) / TM;
     g.tile0 = tiles;
     tiles += tm * g.tn;
     tmap.insert(tmap.end(), size_t(tm * g.tn), int32_t(d.size()));
@@ -610,6 +613,10 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     d.sx = 2.0 / sc.first;
     d.sy = 2.0 / sc.second;
     d.info = i;
+    // the p = 16 leaf kernel forms H itself (its padding rows hold D_ge,ci)
+    d.hrows = leaf_kernel_forms_h(p, g4) ? g4 : 0;
+    d.Dci = Lo.Dci[size_t(pl.leaf_class[i]) * 5 + pl.boxes[li].role];
+    d.H = Lo.H[li];
     leafd.push_back(d);
   }
   // the leaves whose operators the build computes (all but deduplicated
@@ -644,13 +651,15 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       g.C = ref(BUF_SCR, Lo.B_scr[li], mi); g.D = noref();
       g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
       a.add(g);
-      // H = D_ge,ci F
-      g = GemmDesc{};
-      g.M = g4; g.N = mi; g.K = mi;
-      g.A = ref(BUF_WS, Dci, g4); g.B = F;
-      g.C = ref(BUF_WS, Lo.H[li], g4); g.D = noref();
-      g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
-      a.add(g);
+      // H = D_ge,ci F (unless the leaf kernel formed it)
+      if (!leaf_kernel_forms_h(p, g4)) {
+        g = GemmDesc{};
+        g.M = g4; g.N = mi; g.K = mi;
+        g.A = ref(BUF_WS, Dci, g4); g.B = F;
+        g.C = ref(BUF_WS, Lo.H[li], g4); g.D = noref();
+        g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
+        a.add(g);
+      }
       // S_ci = -F B
       g = GemmDesc{};
       g.M = mi; g.N = g4; g.K = mi;
@@ -974,6 +983,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       for (int i = 0; i < nleaf; ++i) {
         LeafDesc d = leafd[i];
         d.Aie = -1;
+        d.hrows = 0;                  // H is stored already
         leafd.push_back(d);
       }
       for (int c0 = 0; c0 < nleaf; c0 += H->econ_chunk) {
@@ -1310,13 +1320,16 @@ Bases make_bases(hps_handle *H) {
 // Algorithmic work of each launch step, from the host descriptor lists.
 static void annotate_work(std::vector<Step> &prog, const GemmList &gl,
                           const std::vector<MergeInvDesc> &mv,
-                          const std::vector<ApplyDesc> &ap, int mi) {
+                          const std::vector<ApplyDesc> &ap, int mi, int p, int g4) {
+  // the leaf kernel's work: the inverse, and H = D_ge,ci F where it forms H
+  const double leaf_w = 2.0 * double(mi) * mi * mi +
+                        (leaf_kernel_forms_h(p, g4) ? 2.0 * double(g4) * mi * mi : 0.0);
   for (Step &s : prog) {
     double w = 0.0;
     for (int64_t i = s.d0; i < s.d0 + s.nd; ++i) {
       switch (s.kind) {
         case S_GEMM: w += 2.0 * gl.d[i].M * double(gl.d[i].N) * gl.d[i].K; break;
-        case S_GJ_LEAF: w += 2.0 * double(mi) * mi * mi; break;
+        case S_GJ_LEAF: w += leaf_w; break;
         case S_GJ_MERGE: w += 2.0 * double(mv[i].m) * mv[i].m * mv[i].m; break;
         case S_PANEL: {
           // update by panel kb of the other columns, sweep of panel kb + NB
@@ -1337,6 +1350,135 @@ static void annotate_work(std::vector<Step> &prog, const GemmList &gl,
   }
 }
 
+// Per tile variant: the GEMM descriptors re-tiled for that variant's
+// TM x TN tiles and the tile maps of every GEMM step of every program (a
+// step's tile0 and tile map are relative to its own first descriptor).
+static_assert(kGemmVariants <= 8, "Step keeps at most eight tile variants");
+static int upload_gemm_variants(hps_handle *H, const std::vector<GemmDesc> &d0,
+                                std::vector<std::vector<Step> *> progs) {
+  for (int v = 0; v < kGemmVariants; ++v) {
+    const int TM = gemm_variant_tm(v), TN = gemm_variant_tn(v);
+    std::vector<GemmDesc> dv = d0;
+    std::vector<int32_t> tv;
+    for (std::vector<Step> *prog : progs)
+      for (Step &s : *prog) {
+        if (s.kind != S_GEMM) continue;
+        s.vtmap0[v] = (int64_t)tv.size();
+        int64_t t = 0;
+        for (int64_t i = s.d0; i < s.d0 + s.nd; ++i) {
+          GemmDesc &g = dv[size_t(i)];
+          g.tn = (g.N + TN - 1) / TN;
+          const int64_t tm = (g.M + TM - 1) / TM;
+          g.tile0 = t;
+          t += tm * g.tn;
+          tv.insert(tv.end(), size_t(tm * g.tn), int32_t(i - s.d0));
+        }
+        s.vtiles[v] = t;
+      }
+    HIPCHK(H->d_gemm_v[v].upload(dv));
+    HIPCHK(H->d_gemm_tmap_v[v].upload(tv));
+  }
+  return HPS_OK;
+}
+
+// GEMM tile tuner.  The first build of a handle times every tile variant on
+// each GEMM step of its program (two launches after a warm-up, HIP events)
+// and keeps the fastest; all variants compute bitwise the same result, so
+// the choice never changes the operators.  Winners are cached per process,
+// keyed by the device architecture and the step's shape class (descriptor
+// count, first descriptor's M x N x K, the step's 64 x 64 tile count), and,
+// when HPS_GEMM_TUNE_CACHE names a file, read from and appended to it.
+// HPS_GEMM_TUNE=0 switches tuning off (64 x 64 tiles everywhere).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Step &s, const GemmDesc &g0) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "gpu";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  const size_t c = arch.find(':');
+  if (c != std::string::npos) arch.resize(c);
+  return arch + " " + std::to_string(s.nd) + " " + std::to_string(g0.M) + "x" +
+         std::to_string(g0.N) + "x" + std::to_string(g0.K) + " " + std::to_string(s.vtiles[0]);
+}
+
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("HPS_GEMM_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t bar = line.rfind('|');
+    if (bar == std::string::npos) continue;
+    g_tune[line.substr(0, bar)] = std::atoi(line.c_str() + bar + 1);
+  }
+}
+
+void tune_cache_store(const std::string &key, int v) {
+  g_tune[key] = v;
+  const char *path = std::getenv("HPS_GEMM_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream out(path, std::ios::app);
+  out << key << "|" << v << "\n";
+}
+}  // namespace
+
+static bool gemm_tuning_enabled() {
+  const char *e = std::getenv("HPS_GEMM_TUNE");
+  return !(e && e[0] == '0');
+}
+
+static int tune_gemm_step(hps_handle *H, Step &s, const Bases &bs, hipStream_t st) {
+  GemmDesc g0{};
+  HIPCHK(hipMemcpy(&g0, H->d_gemm_v[0].p + s.d0, sizeof(GemmDesc), hipMemcpyDeviceToHost));
+  const std::string key = tune_key(s, g0);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      s.var = it->second;
+      return HPS_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 0.0f;
+  int bv = 0;
+  hipError_t err = hipSuccess;
+  for (int v = 0; v < kGemmVariants && err == hipSuccess; ++v) {
+    auto go = [&]() {
+      return launch_gemm(v, H->d_gemm_v[v].p + s.d0, H->d_gemm_tmap_v[v].p + s.vtmap0[v],
+                         s.vtiles[v], bs, st);
+    };
+    err = go();
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && err == hipSuccess; ++r) err = go();
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && (v == 0 || ms < best)) {
+      best = ms;
+      bv = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(HPS_EHIP, std::string("GEMM tuning: ") + hipGetErrorString(err));
+  s.var = bv;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache_store(key, bv);
+  return HPS_OK;
+}
+
 static hipEvent_t prof_event(hps_handle *H) {
   if (H->prof_used == H->prof_pool.size()) {
     hipEvent_t e;
@@ -1346,9 +1488,13 @@ static hipEvent_t prof_event(hps_handle *H) {
   return H->prof_pool[H->prof_used++];
 }
 
-int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, int prec,
+int run_prog(hps_handle *H, std::vector<Step> &prog, Bases bs, int nrhs, int prec,
              hipStream_t st) {
-  for (const Step &s : prog) {
+  for (Step &s : prog) {
+    if (s.kind == S_GEMM && H->tune_gemm) {
+      const int rc = tune_gemm_step(H, s, bs, st);
+      if (rc) return rc;
+    }
     hipError_t e = hipSuccess;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (H->prof_on) {
@@ -1358,7 +1504,8 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
     }
     switch (s.kind) {
       case S_GEMM:
-        e = launch_gemm(H->d_gemm.p + s.d0, H->d_gemm_tmap.p + s.tmap0, s.ntiles, bs, st);
+        e = launch_gemm(s.var, H->d_gemm_v[s.var].p + s.d0,
+                        H->d_gemm_tmap_v[s.var].p + s.vtmap0[s.var], s.vtiles[s.var], bs, st);
         break;
       case S_GJ_LEAF:
         e = launch_gj_leaf(H->p, H->d_leaf.p + s.d0, (int)s.nd, bs, H->aux.p + H->Dh_off,
@@ -1395,7 +1542,7 @@ int run_prog(hps_handle *H, const std::vector<Step> &prog, Bases bs, int nrhs, i
     if (e != hipSuccess) return fail(HPS_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     if (H->prof_on && e0 && e1) {
       (void)hipEventRecord(e1, st);
-      int kind = int(s.kind) * 16 + (s.kind == S_GJ_MERGE ? s.cls : 0);
+      int kind = int(s.kind) * 16 + (s.kind == S_GJ_MERGE ? s.cls : s.kind == S_GEMM ? s.var : 0);
       if (s.kind == S_APPLY) kind += prec;
       H->prof_ev.push_back({kind, {e0, e1}});
       H->prof_work.push_back(s.work);
@@ -1420,18 +1567,11 @@ static int check_constant_coeffs(hps_handle *H, const double *coeffs, hipStream_
   return HPS_OK;
 }
 
-size_t hps_build_workspace_size(const hps_tree *tree, int p, int q) {
-  return hps_build_workspace_size_econ(tree, p, q, 0);
-}
-
-size_t hps_build_workspace_size_econ(const hps_tree *tree, int p, int q, int economic) {
-  return hps_build_workspace_size_opts(tree, p, q, economic, 0);
-}
-
-size_t hps_build_workspace_size_opts(const hps_tree *tree, int p, int q, int economic,
-                                     int translation_invariant) {
+size_t hps_build_workspace_size(const hps_tree *tree, int p, const hps_build_opts *opts) {
   if (!tree || p < 4) return 0;
-  if (q <= 0) q = p - 1;
+  int q = opts && opts->q > 0 ? opts->q : p - 1;
+  const int economic = opts ? opts->economic : 0;
+  const int translation_invariant = opts ? opts->translation_invariant : 0;
   hps_handle H;
   H.tree = tree->t;
   H.econ = economic != 0;
@@ -1514,11 +1654,22 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   if (rc) return rc;
   for (auto *prog : {&H->build_prog, &H->up_prog, &H->down_prog, &H->adj_down_prog,
                      &H->adj_up_prog, &H->up_jump_prog, &H->ext_prog})
-    annotate_work(*prog, gl, minv, appl, H->mi);
+    annotate_work(*prog, gl, minv, appl, H->mi, H->p, H->g4);
   H->solve_elems = (size_t)Lo.solve_ws;
   H->scr_build = Lo.scr + 64;
-  if (H->ws.alloc(Lo.ws) != hipSuccess || H->scr.alloc(Lo.scr + 64) != hipSuccess)
+  if (opts && opts->workspace) {
+    const size_t need = size_t(Lo.ws) * sizeof(double);
+    if (opts->workspace_bytes < need)
+      return fail(HPS_EINVAL, "workspace holds " + std::to_string(opts->workspace_bytes) +
+                                  " bytes; the operators need " + std::to_string(need));
+    if (reinterpret_cast<uintptr_t>(opts->workspace) % 256 != 0)
+      return fail(HPS_EINVAL, "workspace must be 256-byte aligned");
+    H->ws.borrow(static_cast<double *>(opts->workspace), size_t(Lo.ws));
+  } else if (H->ws.alloc(Lo.ws) != hipSuccess) {
     return fail(HPS_ENOMEM, "device allocation of the operator workspace");
+  }
+  if (H->scr.alloc(Lo.scr + 64) != hipSuccess)
+    return fail(HPS_ENOMEM, "device allocation of the build scratch");
   HIPCHK(H->imap.upload(imap));
   HIPCHK(H->aux.upload(aux_init));
   HIPCHK(H->info.alloc(H->n_info));
@@ -1528,8 +1679,10 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   for (auto &bl : blocks)
     HIPCHK(hipMemcpy(H->ws.p + bl.first, bl.second.data(), bl.second.size() * sizeof(double),
                      hipMemcpyHostToDevice));
-  HIPCHK(H->d_gemm.upload(gl.d));
-  HIPCHK(H->d_gemm_tmap.upload(gl.tmap));
+  rc = upload_gemm_variants(H.get(), gl.d, {&H->build_prog, &H->up_prog, &H->down_prog,
+                                            &H->adj_down_prog, &H->adj_up_prog,
+                                            &H->up_jump_prog, &H->ext_prog});
+  if (rc) return rc;
   HIPCHK(H->d_leaf.upload(leafd));
   HIPCHK(H->d_minv.upload(minv));
   HIPCHK(H->d_apply.upload(appl));
@@ -1546,7 +1699,9 @@ int hps_build(const hps_tree *tree, const double *coeffs, int p, const hps_build
   HIPCHK(H->coef.alloc(ncoef));
   HIPCHK(hipMemcpyAsync(H->coef.p, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, st));
   Bases bs = make_bases(H.get());
+  H->tune_gemm = gemm_tuning_enabled();
   rc = run_prog(H.get(), H->build_prog, bs, 1, 0, st);
+  H->tune_gemm = false;
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));
   std::vector<int32_t> info(H->n_info);
@@ -1754,25 +1909,32 @@ extern "C" int hps_solve(hps_handle *h, const double *f, const double *g, int nr
 // ---------------------------------------------------------------------------
 // test hooks (include/hps_debug.h)
 // ---------------------------------------------------------------------------
-extern "C" int hps_debug_gemm(int M, int N, int K, double alpha, const double *A, int lda,
-                              const double *B, int ldb, double *C, int ldc, void *stream) {
+extern "C" int hps_debug_gemm_variant(int variant, int M, int N, int K, double alpha,
+                                      const double *A, int lda, const double *B, int ldb,
+                                      double *C, int ldc, void *stream) {
   if (M <= 0 || N <= 0 || K < 0 || !A || !B || !C) return fail(HPS_EINVAL, "bad gemm arguments");
+  if (variant < 0 || variant >= kGemmVariants) return fail(HPS_EINVAL, "no such GEMM variant");
   hipStream_t st = (hipStream_t)stream;
   GemmList gl;
   GemmDesc g{};
   g.M = M; g.N = N; g.K = K;
   g.A = ref(BUF_IN0, 0, lda); g.B = ref(BUF_IN1, 0, ldb); g.C = ref(BUF_IN2, 0, ldc);
   g.D = noref(); g.crow = g.ccol = -1; g.alpha = alpha; g.beta = 0.0;
-  gl.add(g);
+  gl.add(g, gemm_variant_tm(variant), gemm_variant_tn(variant));
   DevArray<GemmDesc> dd;
   DevArray<int32_t> dt;
   HIPCHK(dd.upload(gl.d));
   HIPCHK(dt.upload(gl.tmap));
   Bases bs{};
   bs.d[BUF_IN0] = (void *)A; bs.d[BUF_IN1] = (void *)B; bs.d[BUF_IN2] = (void *)C;
-  HIPCHK(launch_gemm(dd.p, dt.p, gl.tiles, bs, st));
+  HIPCHK(launch_gemm(variant, dd.p, dt.p, gl.tiles, bs, st));
   HIPCHK(hipStreamSynchronize(st));
   return HPS_OK;
+}
+
+extern "C" int hps_debug_gemm(int M, int N, int K, double alpha, const double *A, int lda,
+                              const double *B, int ldb, double *C, int ldc, void *stream) {
+  return hps_debug_gemm_variant(0, M, N, K, alpha, A, lda, B, ldb, C, ldc, stream);
 }
 
 extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, void *stream) {
@@ -1802,8 +1964,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   std::vector<Step> prog;
   emit_inverse_steps(lev, minv, prog);
   HIPCHK(H.d_minv.upload(minv));
-  HIPCHK(H.d_gemm.upload(gl.d));
-  HIPCHK(H.d_gemm_tmap.upload(gl.tmap));
+
   Bases bs = make_bases(&H);
   int rc = run_prog(&H, prog, bs, 1, 0, st);
   if (rc) return rc;
@@ -1816,6 +1977,18 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
     if (info[b] > 0) return fail(HPS_ESINGULAR, "zero pivot in matrix " + std::to_string(b));
     if (info[b] < 0) return fail(HPS_ENONFINITE, "non-finite pivot in matrix " + std::to_string(b));
   }
+  return HPS_OK;
+}
+
+extern "C" int hps_debug_gemm_choices(const hps_handle *h, int *out, int max_n, int *count) {
+  if (!h || !count) return fail(HPS_EINVAL, "NULL argument");
+  int n = 0;
+  for (const Step &s : h->build_prog)
+    if (s.kind == S_GEMM) {
+      if (out && n < max_n) out[n] = s.var;
+      ++n;
+    }
+  *count = n;
   return HPS_OK;
 }
 

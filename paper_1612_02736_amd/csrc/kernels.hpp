@@ -18,9 +18,15 @@ constexpr int kEconChunk = 1024;
 // info code of a leaf Gauss-Jordan whose flag-synchronised sweep gave up
 // waiting (never in a correct run)
 constexpr int kGjSyncTimeout = -0x7fffffff;
-hipError_t launch_gemm(const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
+constexpr int kGemmVariants = 8;  // tile shapes of the grouped GEMM (see gemm_variant_tm/tn)
+int gemm_variant_tm(int v);
+int gemm_variant_tn(int v);
+hipError_t launch_gemm(int variant, const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
                        const Bases &bs, hipStream_t st);
 int gj_leaf_supported(int p);
+// the leaf kernel of order p forms H = D_ge,ci F itself (4q rows fit in its
+// padding rows)
+inline bool leaf_kernel_forms_h(int p, int g4) { return p == 16 && 196 + g4 <= 256; }
 hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
                           const double *Dh, const double *Dh2, const int32_t *ice,
                           int me, int32_t *info, hipStream_t st);

@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "kernels_ext.hpp"
+#include "kernel_util.hpp"
 
 namespace hps {
 
@@ -82,6 +83,115 @@ __global__ __launch_bounds__(256) void residual_kernel(
       flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
     }
     __syncthreads();   // u, dx, dy are rewritten for the next right-hand side
+  }
+}
+
+// p = 16: the same residual with the derivative products as 16 x 16 matrix
+// products on the matrix cores.  With U(iy, ix) = u[iy * 16 + ix] and Dh the
+// reference first-derivative matrix (row-major), Dh2 = Dh^2:
+//   Ux = U Dh^T, Uxx = U Dh2^T, Uy = Dh U, Uyy = Dh2 U, Uxy = Dh Ux.
+// One workgroup of four wavefronts per leaf; wavefront w takes the
+// right-hand sides w, w + 4, ...  Layouts of v_mfma_f64_16x16x4: lane l
+// supplies A[l & 15][k0 + (l >> 4)] and B[k0 + (l >> 4)][l & 15], and result
+// register v of lane l is entry ((l >> 4) + 4 v, l & 15).  The A fragment of
+// Dh, Dh[l & 15][k0 + (l >> 4)], is also the B fragment of Dh^T, and the B
+// fragment of U at k-step v is U at result entry v, so u is read once.  Ux
+// and Uy pass through the wavefront's own LDS tile (for Uxy and the fluxes).
+template <bool SHIFT>
+__global__ __launch_bounds__(256) void residual16_kernel(
+    const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
+    const double *__restrict__ uc, const double *__restrict__ g, double sigma,
+    double *__restrict__ r1, double *__restrict__ flux, const double *__restrict__ Dh_g,
+    const double *__restrict__ Dh2_g, const double *__restrict__ Lloc_g, int q, int nrhs) {
+  constexpr int P = 16, PP = P * P, PI = P - 2, MI = PI * PI;
+  __shared__ double Wx[4][P][P + 1], Wy[4][P][P + 1];
+  __shared__ double Ll[P * P];
+  const int leaf = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t nl = nleaf;
+  const LeafDesc &d = leafd[leaf];
+  const double sx = d.sx, sy = d.sy;
+  double fD[4], fD2[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    fD[kk] = Dh_g[li * P + 4 * kk + lk];
+    fD2[kk] = Dh2_g[li * P + 4 * kk + lk];
+  }
+  // coefficients at this lane's result entries, folded with the scalings
+  double a0[4], a1[4], a2[4], a3[4], a4[4], a5[4];
+  const double *cl = coef + int64_t(leaf) * 6 * PP;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int t = (lk + 4 * v) * P + li;
+    a0[v] = -cl[t] * sx * sx;
+    a1[v] = -2.0 * cl[PP + t] * sx * sy;
+    a2[v] = -cl[2 * PP + t] * sy * sy;
+    a3[v] = cl[3 * PP + t] * sx;
+    a4[v] = cl[4 * PP + t] * sy;
+    a5[v] = cl[5 * PP + t];
+  }
+  if (!SHIFT)
+    for (int i = tid; i < q * P; i += 256) Ll[i] = Lloc_g[i];
+  __syncthreads();
+  for (int r = w; r < nrhs; r += 4) {
+    const double *u = uc + (int64_t(r) * nl + leaf) * PP;
+    double uA[4], uB[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      uA[kk] = u[li * P + 4 * kk + lk];
+      uB[kk] = u[(4 * kk + lk) * P + li];
+    }
+    dbl4 ux = {0.0, 0.0, 0.0, 0.0}, uxx = ux, uy = ux, uyy = ux, uxy = ux;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      ux = __builtin_amdgcn_mfma_f64_16x16x4f64(uA[kk], fD[kk], ux, 0, 0, 0);
+      uxx = __builtin_amdgcn_mfma_f64_16x16x4f64(uA[kk], fD2[kk], uxx, 0, 0, 0);
+      uy = __builtin_amdgcn_mfma_f64_16x16x4f64(fD[kk], uB[kk], uy, 0, 0, 0);
+      uyy = __builtin_amdgcn_mfma_f64_16x16x4f64(fD2[kk], uB[kk], uyy, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wx[w][lk + 4 * v][li] = ux[v];
+      Wy[w][lk + 4 * v][li] = uy[v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      uxy = __builtin_amdgcn_mfma_f64_16x16x4f64(fD[kk], Wx[w][4 * kk + lk][li], uxy, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = lk + 4 * v, col = li;
+      if (row >= 1 && row <= PI && col >= 1 && col <= PI) {
+        const double Au = a0[v] * uxx[v] + a1[v] * uxy[v] + a2[v] * uyy[v] + a3[v] * ux[v] +
+                          a4[v] * uy[v] + a5[v] * uB[v];
+        const int64_t o = (int64_t(r) * nl + leaf) * MI + (row - 1) * PI + (col - 1);
+        if constexpr (SHIFT) r1[o] = sigma * uB[v] - Au;
+        else r1[o] = g[o] - Au;
+      }
+    }
+    if constexpr (!SHIFT) {
+      for (int k = lane; k < 4 * q; k += 64) {
+        const int side = k / q, kk = k - side * q;
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const double l = Ll[kk * P + j];
+          const double dv = side == 0 ? sy * Wy[w][0][j]
+                          : side == 1 ? sx * Wx[w][j][P - 1]
+                          : side == 2 ? sy * Wy[w][P - 1][j]
+                                      : sx * Wx[w][j][0];
+          v = fma(l, dv, v);
+        }
+        flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
+      }
+    }
+    // this wavefront's LDS tiles are rewritten by its next right-hand side
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -187,6 +297,11 @@ static hipError_t launch_residual_t(int p, const LeafDesc *leafd, int nleaf, con
                                     double *flux, const double *Dh, const double *Dh2,
                                     const double *Lloc, int q, int nrhs, hipStream_t st) {
   dim3 grid(nleaf);
+  if (p == 16) {
+    hipLaunchKernelGGL((residual16_kernel<SHIFT>), grid, dim3(256), 0, st, leafd, nleaf, coef, uc,
+                       g, sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
+    return hipGetLastError();
+  }
   switch (p) {
 #define HPS_RES_CASE(PV)                                                                      \
     case PV:                                                                                  \

@@ -145,12 +145,56 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
 }
 
 
-hipError_t launch_gemm(const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
+// Tile variants (TM x TN per workgroup, K chunk): 0: 64 x 64, 1: 128 x 64,
+// 2: 64 x 128, 3: 128 x 128, 4: 32 x 32, 5: 64 x 32, 6: 32 x 64 (K chunks
+// of 16), 7: 64 x 64 with K chunks of 8 (half the LDS of variant 0, so more
+// workgroups per CU).  Every variant accumulates each output over k in the
+// same order (k-steps of 4, ascending), so all give bitwise the same result.
+static const int kVarTM[8] = {64, 128, 64, 128, 32, 64, 32, 64};
+static const int kVarTN[8] = {64, 64, 128, 128, 32, 32, 64, 64};
+int gemm_variant_tm(int v) { return kVarTM[v]; }
+int gemm_variant_tn(int v) { return kVarTN[v]; }
+
+hipError_t launch_gemm(int variant, const GemmDesc *descs, const int32_t *tmap, int64_t ntiles,
                        const Bases &bs, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  const int64_t nblk = (ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 1>), dim3(unsigned(nblk)), dim3(256), 0, st,
-                     descs, tmap, ntiles, bs);
+  const dim3 grid(unsigned((ntiles + 7) / 8 * 8));
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 1:
+      hipLaunchKernelGGL((gemm_f64_kernel<128, 64, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 128, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 3:
+      hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 4:
+      hipLaunchKernelGGL((gemm_f64_kernel<32, 32, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 5:
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 32, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 6:
+      hipLaunchKernelGGL((gemm_f64_kernel<32, 64, 16, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    case 7:
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 8, 1>), grid, dim3(256), 0, st, descs, tmap,
+                         ntiles, bs);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -231,12 +231,15 @@ __global__ __launch_bounds__(NT) void gj_step_kernel(
   if (sweep && tid == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
 }
 
-// stepof = -1 before the first panel
+// stepof = -1 before the first panel; pivrow[k] = k (in range even if a
+// failed build leaves a step without a pivot)
 __global__ __launch_bounds__(256) void gj_ginit_kernel(const MergeInvDesc *__restrict__ descs,
                                                        int nd, int32_t *__restrict__ g_all) {
   const MergeInvDesc &d = descs[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x) {
+    g_all[d.ipiv + i] = i;
     g_all[d.ipiv + d.m + i] = -1;
+  }
 }
 
 // Inverse from the swept matrix: X[i][j] = M[pivrow[i]][stepof[j]], through a
@@ -256,7 +259,8 @@ __global__ __launch_bounds__(256) void gj_perm_kernel(const MergeInvDesc *__rest
       Y[e] = X[e];
     } else {
       const int64_t col = e / n, row = e - col * n;
-      X[e] = Y[pivrow[row] + int64_t(stepof[col]) * n];
+      const int sc = stepof[col];              // < 0 only after a failed sweep
+      X[e] = Y[pivrow[row] + int64_t(sc < 0 ? 0 : sc) * n];
     }
   }
 }

@@ -93,6 +93,12 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
       Aie[idx] = entry(grid_of(a), ice[e]);
     }
   }
+  // rows MI .. MI + hrows - 1 (padding rows otherwise) carry D_ge,ci: they
+  // are never pivots, and the sweeps turn them into -D_ge,ci A_ci,ci^-1 = -H
+  // (with the columns in pivot order), the flux map of the particular
+  // solution (Sec. 3.4), so H needs no product with the stored F
+  const int hrows = d.hrows;
+  const double *Dci = (const double *)bs.d[BUF_WS] + d.Dci;
   double a[RA][CB];
 #pragma unroll
   for (int i = 0; i < RA; ++i) {
@@ -100,10 +106,28 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       const int col = wid + NW * b;
-      a[i][b] = (row < MI && col < MI) ? entry(grid_of(row), grid_of(col)) : 0.0;
+      double v = 0.0;
+      if (col < MI) {
+        if (row < MI) v = entry(grid_of(row), grid_of(col));
+        else if (row - MI < hrows) v = Dci[(row - MI) + int64_t(col) * hrows];
+      }
+      a[i][b] = v;
     }
   }
   gj2_core<NW, RA, CB>(a, MI, lane, wid, sh);
+  if (hrows > 0) {
+    double *Hp = (double *)bs.d[BUF_WS] + d.H;
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      const int row = lane + 64 * i;
+      if (row < MI || row - MI >= hrows) continue;
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int col = wid + NW * b;
+        if (col < MI) Hp[(row - MI) + int64_t(sh.pivrow[col]) * hrows] = -a[i][b];
+      }
+    }
+  }
   double *F = (double *)bs.d[d.fbuf] + d.F;
 #pragma unroll
   for (int i = 0; i < RA; ++i) {

@@ -77,8 +77,14 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
   HIPCHK(launch_accumulate(E.xug.p, 0, vug, 0, nug, 1, 0, st));
   rc = recompute_exterior(H, u, nrhs, st);
   if (rc) return rc;
+  // Stopping rule: each FP32 sweep solves the correction equation to a
+  // relative accuracy rho (about 1e-6), so after a correction du the error is
+  // about rho |du|.  rho is estimated as the ratio of successive corrections
+  // (the first "correction" being the first sweep's u itself), and the
+  // refinement stops once the size of the last correction or, with a safety
+  // factor of 100, that estimate of the remaining error is at most ir_tol.
   int it = 0;
-  double ratio = 1.0;
+  double ratio = 1.0, prev = 1.0;
   for (; it < max_iter; ++it) {
     HIPCHK(launch_residual(H->p, H->d_leaf.p, H->nleaf, H->coef.p, u, g, 0.0, E.r1.p, E.flux.p,
                            H->aux.p + H->Dh_off, H->aux.p + H->Dh2_off, H->d_lloc.p, H->q, nrhs,
@@ -99,7 +105,13 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
     if (!std::isfinite(m[0]) || !std::isfinite(m[1]))
       return fail(HPS_ENONFINITE, "non-finite entry in the refined solution or its correction");
     ratio = m[1] > 0.0 ? m[0] / m[1] : (m[0] > 0.0 ? HUGE_VAL : 0.0);
-    if (ratio <= tol) { ++it; break; }
+    const double rho = prev > 0.0 ? ratio / prev : HUGE_VAL;
+    prev = ratio;
+    if (ratio <= tol || (rho <= 1e-3 && 100.0 * rho * ratio <= tol)) {
+      ratio = std::min(ratio, rho * ratio);
+      ++it;
+      break;
+    }
   }
   if (opts && opts->iters_out) *opts->iters_out = it;
   if (opts && opts->resid_out) *opts->resid_out = ratio;

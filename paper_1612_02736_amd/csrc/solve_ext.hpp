@@ -11,6 +11,6 @@ int solve_ext_mixed(hps_handle *H, const double *f, const double *g, int nrhs, d
 int hps_solve_pass(hps_handle *H, const double *f, const double *g, int nrhs, double *u,
                    int prec, const double *jump, hipStream_t st);
 hps::Bases make_bases(hps_handle *H);
-int run_prog(hps_handle *H, const std::vector<hps::Step> &prog, hps::Bases bs, int nrhs,
+int run_prog(hps_handle *H, std::vector<hps::Step> &prog, hps::Bases bs, int nrhs,
              int prec, hipStream_t st);
 int ensure_solve_buffers(hps_handle *H, int nrhs);

@@ -52,6 +52,11 @@ struct LeafDesc {
   double sx, sy;  // 2/hx, 2/hy
   int32_t info;   // slot in the info array
   int32_t fbuf;   // buffer of F: BUF_WS (stored) or BUF_SCR (recomputed per chunk)
+  // p = 16 kernel: H = D_ge,ci F formed in the same sweeps (hrows = 4q rows
+  // of D_ge,ci at BUF_WS offset Dci and of H at offset H, both ld hrows);
+  // hrows = 0: H is not formed here
+  int64_t Dci, H;
+  int32_t hrows, pad;
 };
 
 // Interface block of a merge: X = (T33a - T33b)^-1.

@@ -24,8 +24,7 @@ _ERRS = {-1: "HPS_EINVAL", -2: "HPS_ETREE", -3: "HPS_ESINGULAR",
 EXPORTS = ["hps_tree_uniform", "hps_tree_refine_point", "hps_tree_set_bc", "hps_tree_info",
            "hps_tree_counts", "hps_leaf_cheb_nodes", "hps_leaf_boxes",
            "hps_bdry_gauss_nodes", "hps_gauss_nodes", "hps_tree_free",
-           "hps_build", "hps_refactor", "hps_build_workspace_size",
-           "hps_build_workspace_size_econ", "hps_build_workspace_size_opts", "hps_solve",
+           "hps_build", "hps_refactor", "hps_build_workspace_size", "hps_solve",
            "hps_solve_noalloc",
            "hps_solve_adjoint", "hps_coeff_grad_c", "hps_apply_operator",
            "hps_handle_free", "hps_last_error"]
@@ -46,7 +45,8 @@ class TreeInfo(ctypes.Structure):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("keep_fp32", ctypes.c_int), ("economic", ctypes.c_int),
-                ("translation_invariant", ctypes.c_int)]
+                ("translation_invariant", ctypes.c_int), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -82,12 +82,8 @@ def lib():
     L.hps_tree_free.restype = None
     L.hps_build.argtypes = [vp, vp, ip, ctypes.POINTER(BuildOpts), ctypes.POINTER(vp)]
     L.hps_refactor.argtypes = [vp, vp, vp]
-    L.hps_build_workspace_size.argtypes = [vp, ip, ip]
+    L.hps_build_workspace_size.argtypes = [vp, ip, ctypes.POINTER(BuildOpts)]
     L.hps_build_workspace_size.restype = ctypes.c_size_t
-    L.hps_build_workspace_size_econ.argtypes = [vp, ip, ip, ip]
-    L.hps_build_workspace_size_econ.restype = ctypes.c_size_t
-    L.hps_build_workspace_size_opts.argtypes = [vp, ip, ip, ip, ip]
-    L.hps_build_workspace_size_opts.restype = ctypes.c_size_t
     L.hps_solve.argtypes = [vp, vp, vp, ip, vp, ctypes.POINTER(SolveOpts)]
     L.hps_solve_noalloc.argtypes = [vp, vp, vp, ip, vp, ctypes.POINTER(SolveOpts)]
     L.hps_solve_adjoint.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(SolveOpts)]
@@ -187,8 +183,9 @@ class Tree:
         """Device bytes of the operators a build stores (economic: without
         the leaf F, the storage-efficient version of Sec. 5.4;
         translation_invariant: one copy per distinct box)."""
-        return lib().hps_build_workspace_size_opts(self._h, p, q, int(economic),
-                                                   int(translation_invariant))
+        o = BuildOpts(q=q, economic=int(economic),
+                      translation_invariant=int(translation_invariant))
+        return lib().hps_build_workspace_size(self._h, p, ctypes.byref(o))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -200,7 +197,11 @@ class Solver:
     """Handle of a built solution operator (Algorithm 1)."""
 
     def __init__(self, tree, coeffs, p, q=0, keep_fp32=False, economic=False,
-                 translation_invariant=False, stream=None):
+                 translation_invariant=False, stream=None, workspace=None):
+        """workspace: None (the library allocates the operator memory), True
+        (a torch uint8 tensor of tree.workspace_bytes(...) bytes, owned by this
+        Solver) or a contiguous CUDA tensor of at least that many bytes, which
+        the Solver keeps alive."""
         import torch
         self.tree, self.p = tree, p
         self.q = q if q > 0 else p - 1
@@ -208,9 +209,21 @@ class Solver:
         self.n_gauss, self.n_bdry = tree.counts(self.q)
         if tuple(coeffs.shape) != (self.n_leaves, 6, p * p):
             raise ValueError(f"coeffs must be [{self.n_leaves}, 6, {p * p}]")
+        self.workspace = None
+        wp, wb = None, 0
+        if workspace is not None and workspace is not False:
+            if workspace is True:
+                need = tree.workspace_bytes(p, self.q, economic, translation_invariant)
+                workspace = torch.empty(need, dtype=torch.uint8, device=coeffs.device)
+            if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda
+                    and workspace.is_contiguous()):
+                raise TypeError("workspace must be a contiguous CUDA tensor")
+            self.workspace = workspace
+            wp, wb = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
         o = BuildOpts(q=self.q, stream=_stream(stream), keep_fp32=int(keep_fp32),
                       economic=int(economic),
-                      translation_invariant=int(translation_invariant))
+                      translation_invariant=int(translation_invariant),
+                      workspace=wp, workspace_bytes=wb)
         h = ctypes.c_void_p()
         _check(lib().hps_build(tree._h, _dev_ptr(coeffs, "coeffs"), p, ctypes.byref(o),
                                ctypes.byref(h)))
@@ -317,6 +330,8 @@ def _debug_lib():
         vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.hps_debug_gemm.argtypes = [ip, ip, ip, dp, vp, ip, vp, ip, vp, ip, vp]
         L.hps_debug_invert.argtypes = [ip, ip, vp, vp, vp]
+        L.hps_debug_gemm_variant.argtypes = [ip, ip, ip, ip, dp, vp, ip, vp, ip, vp, ip, vp]
+        L.hps_debug_gemm_choices.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_int)]
         L.hps_debug_solve_work_bytes.argtypes = [vp, ip]
         L.hps_debug_solve_work_bytes.restype = ctypes.c_size_t
         L.hps_debug_boxes.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
@@ -326,8 +341,9 @@ def _debug_lib():
     return L
 
 
-def debug_gemm(A, B, alpha=1.0):
-    """C = alpha A B on the library's MFMA GEMM (column-major device copies)."""
+def debug_gemm(A, B, alpha=1.0, variant=0):
+    """C = alpha A B on the library's MFMA GEMM (column-major device copies),
+    tile variant `variant`."""
     import torch
     M, K = A.shape
     K2, N = B.shape
@@ -335,9 +351,20 @@ def debug_gemm(A, B, alpha=1.0):
     Ad = A.t().contiguous()          # column-major storage of A
     Bd = B.t().contiguous()
     C = torch.empty((N, M), dtype=torch.float64, device=A.device)
-    _check(_debug_lib().hps_debug_gemm(M, N, K, alpha, _dev_ptr(Ad, "A"), M, _dev_ptr(Bd, "B"),
-                                       K, _dev_ptr(C, "C"), M, _stream(None)))
+    _check(_debug_lib().hps_debug_gemm_variant(variant, M, N, K, alpha, _dev_ptr(Ad, "A"), M,
+                                               _dev_ptr(Bd, "B"), K, _dev_ptr(C, "C"), M,
+                                               _stream(None)))
     return C.t()
+
+
+def debug_gemm_choices(solver):
+    """Tile variant the tuner chose for each GEMM step of the build program."""
+    L = _debug_lib()
+    n = ctypes.c_int()
+    _check(L.hps_debug_gemm_choices(solver._h, None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(L.hps_debug_gemm_choices(solver._h, _np_ptr(out), n.value, ctypes.byref(n)))
+    return [int(v) for v in out]
 
 
 def debug_invert(A):

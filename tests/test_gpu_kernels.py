@@ -42,6 +42,46 @@ def test_gemm_matches_numpy(M, N, K):
     np.testing.assert_allclose(C.cpu().numpy(), ref, atol=1e-13 * max(1, np.abs(ref).max()))
 
 
+@pytest.mark.parametrize("M,N,K", [(17, 33, 5), (196, 60, 196), (60, 196, 196),
+                                   (300, 260, 301), (960, 130, 961), (2880, 129, 480)])
+def test_gemm_tile_variants_agree_bitwise(M, N, K):
+    """Every tile variant of the grouped GEMM (64 x 64, 128 x 64, 64 x 128,
+    128 x 128, 32 x 32, 64 x 32, 32 x 64 with K chunks of 16, 64 x 64 with K
+    chunks of 8) accumulates each output over k in the same order, so all
+    give bitwise the same product; variant 0 also against numpy."""
+    import torch
+    from paper_1612_02736_amd.hps import debug_gemm
+    rng = np.random.default_rng(M + 7 * N + 11 * K)
+    A = torch.from_numpy(rng.standard_normal((M, K))).cuda()
+    B = torch.from_numpy(rng.standard_normal((K, N))).cuda()
+    print(f"gemm variants {M}x{N}x{K}", flush=True)
+    outs = [debug_gemm(A, B, alpha=0.75, variant=v) for v in range(8)]
+    for v in range(1, 8):
+        assert torch.equal(outs[0], outs[v]), v
+    ref = 0.75 * A.cpu().numpy() @ B.cpu().numpy()
+    np.testing.assert_allclose(outs[0].cpu().numpy(), ref, atol=1e-13 * max(1, np.abs(ref).max()))
+
+
+def test_gemm_tuner_choices_and_cache():
+    """The first build of a handle times the tile variants on every GEMM
+    step and keeps one per step; a second build of the same shapes takes the
+    cached choices and solves bitwise like the first."""
+    import torch
+    from paper_1612_02736_amd.hps import debug_gemm_choices
+    H = _H()
+    t = H.Tree(0, 1, 0, 1, 8, 8)
+    coeffs, f, g, _ = lib_inputs(t, 16, 15, W.varcoeff, W.FourierSolution(3))
+    s1 = H.Solver(t, to_dev(coeffs), 16)
+    c1 = debug_gemm_choices(s1)
+    print(f"tuner choices {c1}", flush=True)
+    assert len(c1) > 0 and all(0 <= v < 8 for v in c1)
+    s2 = H.Solver(t, to_dev(coeffs), 16)
+    assert debug_gemm_choices(s2) == c1
+    u1 = s1.solve(to_dev(f[None]), to_dev(g[None]))
+    u2 = s2.solve(to_dev(f[None]), to_dev(g[None]))
+    assert torch.equal(u1, u2)
+
+
 @pytest.mark.parametrize("n", [1, 5, 32, 33, 64, 100, 128, 196, 197, 240, 500])
 def test_inverse_matches_numpy(n):
     import torch
@@ -55,7 +95,7 @@ def test_inverse_matches_numpy(n):
         assert relerr(X[b], ref) < 1e-10 * np.linalg.cond(A[b]) / n
 
 
-@pytest.mark.parametrize("n", [40, 196, 300, 700])
+@pytest.mark.parametrize("n", [40, 196, 300, 700, 960, 1408, 1920])
 def test_inverse_needs_pivoting(n):
     """One large entry per row and column at random places, the diagonal 0:
     any pivot choice other than the largest candidate meets a zero or tiny
