@@ -339,17 +339,46 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
 
 }  // namespace
 
-// Builds layout, uploads reference matrices and maps, generates programs.
-static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
-                       std::vector<std::pair<int64_t, std::vector<double>>> &ws_blocks,
-                       std::vector<int32_t> &imap, GemmList &gl, std::vector<LeafDesc> &leafd,
-                       std::vector<MergeInvDesc> &minv, std::vector<ApplyDesc> &appl,
-                       std::vector<int32_t> &appl_tmap, std::vector<int32_t> &finlist,
-                       std::vector<VecOpDesc> &vops) {
+// State shared by the planning stages of one handle.
+struct PlanCtx {
+  hps_handle *H;
+  Layout &Lo;
+  std::vector<double> &ws_init;
+  std::vector<std::pair<int64_t, std::vector<double>>> &ws_blocks;
+  std::vector<int32_t> &imap;
+  GemmList &gl;
+  std::vector<LeafDesc> &leafd;
+  std::vector<MergeInvDesc> &minv;
+  std::vector<ApplyDesc> &appl;
+  std::vector<int32_t> &appl_tmap;
+  std::vector<int32_t> &finlist;
+  std::vector<VecOpDesc> &vops;
+  std::vector<int> rep;     // the box whose operators a box shares (itself unless deduplicated)
+  int64_t f_scr = -1;       // economic build: scratch of one chunk's F
+  bool own(int b) const { return rep[size_t(b)] == b; }
+  int64_t imap_put(const std::vector<int32_t> &v) {
+    const int64_t o = (int64_t)imap.size();
+    imap.insert(imap.end(), v.begin(), v.end());
+    return o;
+  }
+  Ref f_ref(int i) const {   // where leaf i's F lives
+    const int mi = H->mi;
+    if (H->econ) return ref(BUF_SCR, f_scr + int64_t(i % H->econ_chunk) * mi * mi, mi);
+    return ref(BUF_WS, Lo.LD[H->pl.leaves[i]] + int64_t(H->g4) * mi, mi);
+  }
+};
+
+// Stage 1: operator and scratch layout, reference matrices, integer maps.
+static int plan_layout(PlanCtx &C) {
+  hps_handle *H = C.H;
+  Layout &Lo = C.Lo;
   Plan &pl = H->pl;
   const int p = H->p, q = H->q, mi = H->mi, me = H->me, g4 = H->g4;
   const int nb = (int)pl.boxes.size();
   const int nleaf = H->nleaf;
+  (void)p; (void)q; (void)mi; (void)me; (void)g4; (void)nb; (void)nleaf;
+  auto &ws_init = C.ws_init;
+  auto &ws_blocks = C.ws_blocks;
   Lo.T.assign(nb, -1); Lo.X.assign(nb, -1); Lo.S.assign(nb, -1); Lo.LD.assign(nb, -1);
   Lo.H.assign(nb, -1); Lo.Pup.assign(nb, -1); Lo.Pdn.assign(nb, -1); Lo.Pups.assign(nb, -1);
   Lo.Tn_scr.assign(nb, -1); Lo.Tmp_scr.assign(nb, -1); Lo.Aie_scr.assign(nb, -1);
@@ -362,11 +391,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   auto ws_take = [&](int64_t n) { int64_t o = Lo.ws; Lo.ws += (n + 31) / 32 * 32; return o; };
   auto scr_take = [&](int64_t n) { int64_t o = Lo.scr; Lo.scr += (n + 31) / 32 * 32; return o; };
   auto vec_take = [&](int64_t n) { int64_t o = Lo.vec; Lo.vec += n; return o; };
-  auto imap_put = [&](const std::vector<int32_t> &v) {
-    int64_t o = (int64_t)imap.size();
-    imap.insert(imap.end(), v.begin(), v.end());
-    return o;
-  };
+  auto imap_put = [&](const std::vector<int32_t> &v) { return C.imap_put(v); };
   auto imap_put64 = [&](const std::vector<int64_t> &v) {
     std::vector<int32_t> w(v.begin(), v.end());
     return imap_put(w);
@@ -375,7 +400,8 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   // the timings of Sec. 7.1): boxes with the same key -- a leaf's size class
   // and role, a merge's children's keys, cut, role and final order -- have
   // identical operators, stored once at the key's first box (rep).
-  std::vector<int> rep(nb);
+  std::vector<int> &rep = C.rep;
+  rep.assign(nb, 0);
   for (int b = 0; b < nb; ++b) rep[b] = b;
   if (H->dedup) {
     std::map<std::vector<int64_t>, int> first;
@@ -401,7 +427,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
       }
     }
   }
-  auto own = [&](int b) { return rep[b] == b; };
+  auto own = [&](int b) { return C.own(b); };
   // --- solve-stage operators first (they are the FP32-copied prefix) ---
   Lo.vec = pl.n_gauss;   // global u at the start of each RHS block
   H->ug_off = 0;
@@ -508,11 +534,7 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
     if (!own(li)) Lo.T[li] = Lo.T[rep[li]];
   // economic build: F of one chunk of leaves at a time (build and solve)
   H->econ_chunk = H->econ ? std::min(nleaf, kEconChunk) : nleaf;
-  const int64_t f_scr = H->econ ? scr_take(int64_t(H->econ_chunk) * mi * mi) : -1;
-  auto f_ref = [&](int i) -> Ref {   // where leaf i's F lives
-    if (H->econ) return ref(BUF_SCR, f_scr + int64_t(i % H->econ_chunk) * mi * mi, mi);
-    return ref(BUF_WS, Lo.LD[pl.leaves[i]] + int64_t(g4) * mi, mi);
-  };
+  C.f_scr = H->econ ? scr_take(int64_t(H->econ_chunk) * mi * mi) : -1;
   for (int b = 0; b < nb; ++b) {
     const Box &B = pl.boxes[b];
     if (B.leaf || !own(b)) continue;
@@ -596,7 +618,24 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   H->Dh_off = 0;
   H->Dh2_off = int64_t(p) * p;
 
-  // ======================= build program =======================
+  return HPS_OK;
+}
+
+// Stage 2: the build program (Algorithm 1): leaf Gauss-Jordan and products,
+// then the merges level by level.
+static int plan_build_program(PlanCtx &C) {
+  hps_handle *H = C.H;
+  Layout &Lo = C.Lo;
+  Plan &pl = H->pl;
+  const int p = H->p, q = H->q, mi = H->mi, me = H->me, g4 = H->g4;
+  const int nb = (int)pl.boxes.size();
+  const int nleaf = H->nleaf;
+  (void)p; (void)q; (void)mi; (void)me; (void)g4; (void)nb; (void)nleaf;
+  auto &gl = C.gl;
+  auto &leafd = C.leafd;
+  auto &minv = C.minv;
+  auto own = [&](int b) { return C.own(b); };
+  auto f_ref = [&](int i) { return C.f_ref(i); };
   auto &prog = H->build_prog;
   prog.clear();
   // leaves: Gauss-Jordan, then the leaf products, one chunk of leaves at a
@@ -784,11 +823,27 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   }
   H->n_info = info_slot;
 
-  // ======================= solve programs =======================
-  const int64_t VS = 0;  // stride placeholder; patched per call through vec_per_rhs
-  (void)VS;
+  return HPS_OK;
+}
+
+// Stage 3: the solve programs (Algorithm 2 and its extensions): upward and
+// downward passes, the refinement-correction and adjoint variants.
+static int plan_solve_programs(PlanCtx &C) {
+  hps_handle *H = C.H;
+  Layout &Lo = C.Lo;
+  Plan &pl = H->pl;
+  const int p = H->p, q = H->q, mi = H->mi, me = H->me, g4 = H->g4;
+  const int nb = (int)pl.boxes.size();
+  const int nleaf = H->nleaf;
+  (void)p; (void)q; (void)mi; (void)me; (void)g4; (void)nb; (void)nleaf;
+  auto &leafd = C.leafd;
+  auto &appl = C.appl;
+  auto &appl_tmap = C.appl_tmap;
+  auto &finlist = C.finlist;
+  auto &vops = C.vops;
+  auto imap_put = [&](const std::vector<int32_t> &v) { return C.imap_put(v); };
+  auto f_ref = [&](int i) { return C.f_ref(i); };
   H->vec_per_rhs = Lo.vec;
-  const int64_t vs = Lo.vec;
   const int64_t gstride = int64_t(nleaf) * mi, ustride = int64_t(nleaf) * p * p;
   int64_t part_off = 0;
   auto apply_step = [&](std::vector<ApplyDesc> &tmp, std::vector<Step> &prg) {
@@ -1302,6 +1357,21 @@ static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
   for (int k = 0; k < maxk; ++k) iota[k] = k;
   H->iota_off = imap_put(iota);
   return HPS_OK;
+}
+
+// Builds layout, uploads reference matrices and maps, generates programs.
+static int plan_handle(hps_handle *H, Layout &Lo, std::vector<double> &ws_init,
+                       std::vector<std::pair<int64_t, std::vector<double>>> &ws_blocks,
+                       std::vector<int32_t> &imap, GemmList &gl, std::vector<LeafDesc> &leafd,
+                       std::vector<MergeInvDesc> &minv, std::vector<ApplyDesc> &appl,
+                       std::vector<int32_t> &appl_tmap, std::vector<int32_t> &finlist,
+                       std::vector<VecOpDesc> &vops) {
+  PlanCtx C{H, Lo, ws_init, ws_blocks, imap, gl, leafd, minv, appl, appl_tmap, finlist, vops,
+            {}, -1};
+  int rc = plan_layout(C);
+  if (rc == HPS_OK) rc = plan_build_program(C);
+  if (rc == HPS_OK) rc = plan_solve_programs(C);
+  return rc;
 }
 
 Bases make_bases(hps_handle *H) {
