@@ -46,7 +46,11 @@ KERNEL_SOURCES = {"gemm": ["kernels_gemm.hip", "kernel_util.hpp"],
                   "gj_leaf": ["kernels_gj_leaf.hip", "gj_core.hpp", "kernel_util.hpp"],
                   "gj_panel": ["kernels_gj_blocked.hip", "gj_core.hpp", "kernel_util.hpp"],
                   "apply": ["kernels_mfma.hip", "kernels_apply.hip", "kernel_util.hpp"]}
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # gj2_leaf_kernel<16, 8, 4, 25>: FETCH_SIZE 57,811 KiB x 2.000 + WRITE_SIZE
+    # 2,096,247 KiB x 1.000 per launch (64 x 64 leaves, p = 16)
+    "gj_leaf[0]": ("cd475fdaa9ae46f9", 2265.0e6),
+}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector = FP64 matrix
 

@@ -12,100 +12,37 @@
 
 namespace hps {
 
-// One workgroup per leaf, looping over the right-hand sides (the leaf's
-// coefficients and reference matrices are read once).  Residual of the
-// collocated PDE at interior nodes, r = g - A u (Sec. 3.2, same A as the
-// build), and the leaf's boundary fluxes D_ge,c u (Sec. 3.4) in side order
-// S, E, N, W.  SHIFT = true returns sigma u - A u instead and no fluxes (the
-// right side of an implicit time step, Sec. 7.6); it is a separate
-// instantiation so that the residual keeps its register budget.
-template <int P, bool SHIFT>
-__global__ __launch_bounds__(256) void residual_kernel(
-    const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
-    const double *__restrict__ uc, const double *__restrict__ g, double sigma,
-    double *__restrict__ r1, double *__restrict__ flux, const double *__restrict__ Dh_g,
-    const double *__restrict__ Dh2_g,
-    const double *__restrict__ Lloc_g, int q, int nrhs) {
-  constexpr int PP = P * P, PI = P - 2, MI = PI * PI;
-  __shared__ double u[PP], dx[PP], dy[PP], Dh[PP], Dh2[PP], cf[6][PP], Lloc[P * P];
-  const int leaf = blockIdx.x, tid = threadIdx.x;
-  const int64_t nl = nleaf;
-  const LeafDesc &d = leafd[leaf];
-  const double sx = d.sx, sy = d.sy;
-  for (int i = tid; i < PP; i += 256) {
-    Dh[i] = Dh_g[i];
-    Dh2[i] = Dh2_g[i];
-  }
-  for (int i = tid; i < q * P; i += 256) Lloc[i] = Lloc_g[i];
-  for (int i = tid; i < 6 * PP; i += 256) cf[i / PP][i % PP] = coef[int64_t(leaf) * 6 * PP + i];
-  for (int r = 0; r < nrhs; ++r) {
-    for (int i = tid; i < PP; i += 256) u[i] = uc[(int64_t(r) * nl + leaf) * PP + i];
-    __syncthreads();
-    // reference-coordinate first derivatives on the whole grid
-    for (int t = tid; t < PP; t += 256) {
-      const int iy = t / P, ix = t - iy * P;
-      double sxv = 0.0, syv = 0.0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        sxv += Dh[ix * P + j] * u[iy * P + j];
-        syv += Dh[iy * P + j] * u[j * P + ix];
-      }
-      dx[t] = sxv;
-      dy[t] = syv;
-    }
-    __syncthreads();
-    for (int a = tid; a < MI; a += 256) {
-      const int y = a / PI, iy = y + 1, ix = a - y * PI + 1, t = iy * P + ix;
-      double uxx = 0.0, uyy = 0.0, uxy = 0.0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        uxx += Dh2[ix * P + j] * u[iy * P + j];
-        uyy += Dh2[iy * P + j] * u[j * P + ix];
-        uxy += Dh[iy * P + j] * dx[j * P + ix];
-      }
-      const double Au = -cf[0][t] * sx * sx * uxx - 2.0 * cf[1][t] * sx * sy * uxy -
-                        cf[2][t] * sy * sy * uyy + cf[3][t] * sx * dx[t] + cf[4][t] * sy * dy[t] +
-                        cf[5][t] * u[t];
-      const int64_t o = (int64_t(r) * nl + leaf) * MI + a;
-      if constexpr (SHIFT) r1[o] = sigma * u[t] - Au;
-      else r1[o] = g[o] - Au;
-    }
-    for (int k = SHIFT ? 4 * q : tid; k < 4 * q; k += 256) {
-      const int side = k / q, kk = k - side * q;
-      double v = 0.0;
-      for (int j = 0; j < P; ++j) {
-        const double l = Lloc[kk * P + j];
-        if (side == 0) v += l * sy * dy[0 * P + j];
-        else if (side == 1) v += l * sx * dx[j * P + (P - 1)];
-        else if (side == 2) v += l * sy * dy[(P - 1) * P + j];
-        else v += l * sx * dx[j * P + 0];
-      }
-      flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
-    }
-    __syncthreads();   // u, dx, dy are rewritten for the next right-hand side
-  }
-}
-
-// p = 16: the same residual with the derivative products as 16 x 16 matrix
-// products on the matrix cores.  With U(iy, ix) = u[iy * 16 + ix] and Dh the
-// reference first-derivative matrix (row-major), Dh2 = Dh^2:
+// FP64 residual of the collocated PDE at interior nodes, r = g - A u
+// (Sec. 3.2, the same A as the build), and the leaf's boundary fluxes
+// D_ge,c u (Sec. 3.4) in side order S, E, N, W.  SHIFT = true returns
+// sigma u - A u instead and no fluxes (the right side of an implicit time
+// step, Sec. 7.6).
+// p <= 16: the same residual with the derivative products as 16 x 16 matrix
+// products on the matrix cores (a p x p grid sits in the top-left corner of
+// a zero-padded 16 x 16 tile, which leaves the products on the grid exact).
+// With U(iy, ix) = u[iy * p + ix] and Dh the reference first-derivative
+// matrix (row-major), Dh2 = Dh^2:
 //   Ux = U Dh^T, Uxx = U Dh2^T, Uy = Dh U, Uyy = Dh2 U, Uxy = Dh Ux.
-// One workgroup of four wavefronts per leaf; wavefront w takes the
-// right-hand sides w, w + 4, ...  Layouts of v_mfma_f64_16x16x4: lane l
-// supplies A[l & 15][k0 + (l >> 4)] and B[k0 + (l >> 4)][l & 15], and result
-// register v of lane l is entry ((l >> 4) + 4 v, l & 15).  The A fragment of
-// Dh, Dh[l & 15][k0 + (l >> 4)], is also the B fragment of Dh^T, and the B
-// fragment of U at k-step v is U at result entry v, so u is read once.  Ux
-// and Uy pass through the wavefront's own LDS tile (for Uxy and the fluxes).
-template <bool SHIFT>
-__global__ __launch_bounds__(256) void residual16_kernel(
+// Workgroup (leaf, j) has four wavefronts; wavefront w takes right-hand side
+// 4 j + w, so every wavefront has one independent chain of loads, products
+// and stores (the four right-hand sides of a leaf share its coefficients
+// through the L2 cache).  Layouts of v_mfma_f64_16x16x4: lane l supplies
+// A[l & 15][k0 + (l >> 4)] and B[k0 + (l >> 4)][l & 15], and result register
+// v of lane l is entry ((l >> 4) + 4 v, l & 15).  The A fragment of Dh,
+// Dh[l & 15][k0 + (l >> 4)], is also the B fragment of Dh^T.  u and g are
+// read and r1 written with coalesced accesses through the wavefront's own
+// LDS tiles; Ux and Uy pass through LDS too (for Uxy and the fluxes).
+template <int P, bool SHIFT>
+__global__ __launch_bounds__(256) void residual_mfma_kernel(
     const LeafDesc *__restrict__ leafd, int nleaf, const double *__restrict__ coef,
     const double *__restrict__ uc, const double *__restrict__ g, double sigma,
     double *__restrict__ r1, double *__restrict__ flux, const double *__restrict__ Dh_g,
     const double *__restrict__ Dh2_g, const double *__restrict__ Lloc_g, int q, int nrhs) {
-  constexpr int P = 16, PP = P * P, PI = P - 2, MI = PI * PI;
-  __shared__ double Wx[4][P][P + 1], Wy[4][P][P + 1];
-  __shared__ double Ll[P * P];
+  static_assert(P >= 4 && P <= 16, "one 16 x 16 tile per grid");
+  constexpr int PP = P * P, PI = P - 2, MI = PI * PI;
+  __shared__ double Us[4][16][17], Wx[4][16][17], Wy[4][16][17];
+  __shared__ double Gs[4][MI];
+  __shared__ double Ll[16 * P];
   const int leaf = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -115,32 +52,45 @@ __global__ __launch_bounds__(256) void residual16_kernel(
   double fD[4], fD2[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
-    fD[kk] = Dh_g[li * P + 4 * kk + lk];
-    fD2[kk] = Dh2_g[li * P + 4 * kk + lk];
+    const int kc = 4 * kk + lk;
+    const bool in = li < P && kc < P;
+    fD[kk] = in ? Dh_g[li * P + kc] : 0.0;
+    fD2[kk] = in ? Dh2_g[li * P + kc] : 0.0;
   }
   // coefficients at this lane's result entries, folded with the scalings
   double a0[4], a1[4], a2[4], a3[4], a4[4], a5[4];
   const double *cl = coef + int64_t(leaf) * 6 * PP;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int t = (lk + 4 * v) * P + li;
-    a0[v] = -cl[t] * sx * sx;
-    a1[v] = -2.0 * cl[PP + t] * sx * sy;
-    a2[v] = -cl[2 * PP + t] * sy * sy;
-    a3[v] = cl[3 * PP + t] * sx;
-    a4[v] = cl[4 * PP + t] * sy;
-    a5[v] = cl[5 * PP + t];
+    const int row = lk + 4 * v;
+    const bool in = row < P && li < P;
+    const int t = in ? row * P + li : 0;
+    a0[v] = in ? -cl[t] * sx * sx : 0.0;
+    a1[v] = in ? -2.0 * cl[PP + t] * sx * sy : 0.0;
+    a2[v] = in ? -cl[2 * PP + t] * sy * sy : 0.0;
+    a3[v] = in ? cl[3 * PP + t] * sx : 0.0;
+    a4[v] = in ? cl[4 * PP + t] * sy : 0.0;
+    a5[v] = in ? cl[5 * PP + t] : 0.0;
   }
+  for (int i = lane; i < 16 * 17; i += 64) (&Us[w][0][0])[i] = 0.0;   // the padding stays 0
   if (!SHIFT)
     for (int i = tid; i < q * P; i += 256) Ll[i] = Lloc_g[i];
   __syncthreads();
-  for (int r = w; r < nrhs; r += 4) {
-    const double *u = uc + (int64_t(r) * nl + leaf) * PP;
+  const int r = int(blockIdx.y) * 4 + w;
+  if (r < nrhs) {
+    const int64_t lr = int64_t(r) * nl + leaf;
+    const double *u = uc + lr * PP;
+    for (int t = lane; t < PP; t += 64) Us[w][t / P][t % P] = u[t];
+    if (!SHIFT)
+      for (int t = lane; t < MI; t += 64) Gs[w][t] = g[lr * MI + t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double uA[4], uB[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      uA[kk] = u[li * P + 4 * kk + lk];
-      uB[kk] = u[(4 * kk + lk) * P + li];
+      uA[kk] = Us[w][li][4 * kk + lk];
+      uB[kk] = Us[w][4 * kk + lk][li];
     }
     dbl4 ux = {0.0, 0.0, 0.0, 0.0}, uxx = ux, uy = ux, uyy = ux, uxy = ux;
 #pragma unroll
@@ -161,17 +111,23 @@ __global__ __launch_bounds__(256) void residual16_kernel(
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
       uxy = __builtin_amdgcn_mfma_f64_16x16x4f64(fD[kk], Wx[w][4 * kk + lk][li], uxy, 0, 0, 0);
+    // the interior residual, staged in Gs (each entry read, then rewritten,
+    // by the one lane that owns it)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = lk + 4 * v, col = li;
       if (row >= 1 && row <= PI && col >= 1 && col <= PI) {
         const double Au = a0[v] * uxx[v] + a1[v] * uxy[v] + a2[v] * uyy[v] + a3[v] * ux[v] +
                           a4[v] * uy[v] + a5[v] * uB[v];
-        const int64_t o = (int64_t(r) * nl + leaf) * MI + (row - 1) * PI + (col - 1);
-        if constexpr (SHIFT) r1[o] = sigma * uB[v] - Au;
-        else r1[o] = g[o] - Au;
+        const int a = (row - 1) * PI + (col - 1);
+        if constexpr (SHIFT) Gs[w][a] = sigma * uB[v] - Au;
+        else Gs[w][a] = Gs[w][a] - Au;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t = lane; t < MI; t += 64) r1[lr * MI + t] = Gs[w][t];
     if constexpr (!SHIFT) {
       for (int k = lane; k < 4 * q; k += 64) {
         const int side = k / q, kk = k - side * q;
@@ -185,13 +141,9 @@ __global__ __launch_bounds__(256) void residual16_kernel(
                                       : sx * Wx[w][j][0];
           v = fma(l, dv, v);
         }
-        flux[(int64_t(r) * nl + leaf) * 4 * q + k] = v;
+        flux[lr * 4 * q + k] = v;
       }
     }
-    // this wavefront's LDS tiles are rewritten by its next right-hand side
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -296,17 +248,12 @@ static hipError_t launch_residual_t(int p, const LeafDesc *leafd, int nleaf, con
                                     const double *uc, const double *g, double sigma, double *r1,
                                     double *flux, const double *Dh, const double *Dh2,
                                     const double *Lloc, int q, int nrhs, hipStream_t st) {
-  dim3 grid(nleaf);
-  if (p == 16) {
-    hipLaunchKernelGGL((residual16_kernel<SHIFT>), grid, dim3(256), 0, st, leafd, nleaf, coef, uc,
-                       g, sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);
-    return hipGetLastError();
-  }
+  dim3 grid(nleaf, (nrhs + 3) / 4);
   switch (p) {
-#define HPS_RES_CASE(PV)                                                                      \
-    case PV:                                                                                  \
-      hipLaunchKernelGGL((residual_kernel<PV, SHIFT>), grid, dim3(256), 0, st, leafd, nleaf,  \
-                         coef, uc, g, sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);               \
+#define HPS_RES_CASE(PV)                                                                       \
+    case PV:                                                                                   \
+      hipLaunchKernelGGL((residual_mfma_kernel<PV, SHIFT>), grid, dim3(256), 0, st, leafd,     \
+                         nleaf, coef, uc, g, sigma, r1, flux, Dh, Dh2, Lloc, q, nrhs);         \
       break;
     HPS_RES_CASE(16)
     HPS_RES_CASE(12)
