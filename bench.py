@@ -43,7 +43,8 @@ N_LEAF_SIDE, P, Q, NRHS = 64, 16, 15, 32
 # source files of that kernel when the counters were taken: a figure is
 # reported only while those sources are unchanged.
 KERNEL_SOURCES = {"gemm": ["kernels_gemm.hip", "kernel_util.hpp"],
-                  "gj_leaf": ["kernels_gj_leaf.hip", "gj_core.hpp", "kernel_util.hpp"],
+                  "gj_leaf": ["kernels_gj_leaf.hip", "kernels_gjb_leaf.hip", "gj_core.hpp",
+                              "kernel_util.hpp"],
                   "gj_panel": ["kernels_gj_blocked.hip", "gj_core.hpp", "kernel_util.hpp"],
                   "apply": ["kernels_mfma.hip", "kernels_apply.hip", "kernel_util.hpp"]}
 MEASURED_TRAFFIC = {

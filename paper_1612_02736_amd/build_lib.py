@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SRC = ["hps_api.cpp", "solve_ext.cpp", "plan.cpp", "spectral.cpp"]
-DEV_SRC = ["kernels_gj_leaf.hip", "kernels_gj_merge.hip", "kernels_gj_blocked.hip",
+DEV_SRC = ["kernels_gj_leaf.hip", "kernels_gjb_leaf.hip", "kernels_gj_merge.hip", "kernels_gj_blocked.hip",
            "kernels_gemm.hip", "kernels_mfma.hip", "kernels_apply.hip",
            "kernels_ext.hip", "noalloc.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

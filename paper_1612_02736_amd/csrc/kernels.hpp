@@ -27,6 +27,9 @@ int gj_leaf_supported(int p);
 // the leaf kernel of order p forms H = D_ge,ci F itself (4q rows fit in its
 // padding rows)
 inline bool leaf_kernel_forms_h(int p, int g4) { return p == 16 && 196 + g4 <= 256; }
+hipError_t launch_gjb_leaf(const LeafDesc *descs, int nleaf, const Bases &bs, const double *Dh,
+                           const double *Dh2, const int32_t *ice, int me, int32_t *info,
+                           hipStream_t st);
 hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
                           const double *Dh, const double *Dh2, const int32_t *ice,
                           int me, int32_t *info, hipStream_t st);

@@ -1,6 +1,9 @@
 // Leaf interior inversions F = A_ci,ci^-1 of the build stage (Sec. 3.3).
 #include "gj_core.hpp"
 
+#include <cstdlib>
+#include <string>
+
 namespace hps {
 
 template <int P, int TR, int TC, int RA, int CB>
@@ -146,12 +149,25 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
 }
 
 
+// p = 16 runs the blocked matrix-core kernel (kernels_gjb_leaf.hip) unless
+// HPS_LEAF_GJ=rank1 selects the column-owner rank-1 kernel above (same
+// outputs up to rounding), kept for comparison.
+static bool leaf_rank1_p16() {
+  static const bool r1 = [] {
+    const char *e = std::getenv("HPS_LEAF_GJ");
+    return e && std::string(e) == "rank1";
+  }();
+  return r1;
+}
+
 hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
                           const double *Dh, const double *Dh2, const int32_t *ice,
                           int me, int32_t *info, hipStream_t st) {
   if (nleaf <= 0) return hipSuccess;
   switch (p) {
     case 16:
+      if (!leaf_rank1_p16())
+        return launch_gjb_leaf(descs, nleaf, bs, Dh, Dh2, ice, me, info, st);
       hipLaunchKernelGGL((gj2_leaf_kernel<16, 8, 4, 25>), dim3(nleaf), dim3(512), 0, st, descs,
                          nleaf, bs, Dh, Dh2, ice, me, info);
       break;

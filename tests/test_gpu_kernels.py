@@ -118,7 +118,7 @@ def test_inverse_needs_pivoting(n):
         assert relerr(X[b], ref) < 1e-12
 
 
-def _build_pair(nx, ny, p, q=None, refine=None):
+def _build_pair(nx, ny, p, q=None, refine=None, coef=W.varcoeff):
     H = _H()
     q = q or p - 1
     t = H.Tree(0, 1, 0, 1, nx, ny)
@@ -127,16 +127,25 @@ def _build_pair(nx, ny, p, q=None, refine=None):
         t.refine_point(0, *refine)
         ot.refine_point(0, *refine)
     sol = W.FourierSolution(1)
-    coeffs, _, _, _ = lib_inputs(t, p, q, W.varcoeff, sol)
+    coeffs, _, _, _ = lib_inputs(t, p, q, coef, sol)
     s = H.Solver(t, to_dev(coeffs), p, q)
-    oc, _, _, _ = make_inputs(ot, p, q, W.varcoeff, sol)
+    oc, _, _, _ = make_inputs(ot, p, q, coef, sol)
     ops = oracle.build(ot, oc, p, q)
     return H, s, ot, ops, p, q
 
 
-@pytest.mark.parametrize("nx,ny,p", [(2, 2, 8), (2, 2, 16), (4, 4, 12)])
-def test_leaf_operators(nx, ny, p):
-    H, s, ot, ops, p, q = _build_pair(nx, ny, p)
+def _helmholtz80(x, y):
+    return W.helmholtz_coeffs(x, y, kappa=80.0)
+
+
+@pytest.mark.parametrize("nx,ny,p,coef", [(2, 2, 8, W.varcoeff), (2, 2, 16, W.varcoeff),
+                                          (4, 4, 12, W.varcoeff), (2, 2, 16, _helmholtz80)])
+def test_leaf_operators(nx, ny, p, coef):
+    """Leaf operators F, S_ci, H and T against the oracle's (Sec. 3); the
+    Helmholtz case (kappa = 80 on leaves of side 1/2) makes A_ci,ci strongly
+    indefinite, so the pivot search leaves the diagonal."""
+    print(f"leaf operators {nx}x{ny} p={p} {coef.__name__}", flush=True)
+    H, s, ot, ops, p, q = _build_pair(nx, ny, p, coef=coef)
     from paper_1612_02736_amd.hps import debug_boxes, debug_box_nodes, debug_box_op
     boxes = debug_boxes(s)
     mi, g4 = (p - 2) ** 2, 4 * q
