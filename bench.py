@@ -48,9 +48,12 @@ KERNEL_SOURCES = {"gemm": ["kernels_gemm.hip", "kernel_util.hpp"],
                   "gj_panel": ["kernels_gj_blocked.hip", "gj_core.hpp", "kernel_util.hpp"],
                   "apply": ["kernels_mfma.hip", "kernels_apply.hip", "kernel_util.hpp"]}
 MEASURED_TRAFFIC = {
-    # gj2_leaf_kernel<16, 8, 4, 25>: FETCH_SIZE 57,811 KiB x 2.000 + WRITE_SIZE
-    # 2,096,247 KiB x 1.000 per launch (64 x 64 leaves, p = 16)
-    "gj_leaf[0]": ("cd475fdaa9ae46f9", 2265.0e6),
+    # gjb_leaf_kernel: FETCH_SIZE 171,449 KiB x 2.000 + WRITE_SIZE 2,363,296 KiB
+    # x 1.000 per launch (64 x 64 leaves, p = 16)
+    "gj_leaf[0]": ("5a0a3d7f43121ceb", 2771.1e6),
+    # gj_step_kernel (all 155 panel launches of a 64 x 64-leaf factorization):
+    # FETCH_SIZE 3,753 KiB x 2.000 + WRITE_SIZE 5,745 KiB x 1.000 per launch
+    "gj_panel[0]": ("0fdec31030b2ee30", 13.57e6),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector = FP64 matrix
@@ -646,7 +649,11 @@ def main():
             roof = {"bound": "alu", "achieved": fl / (avg_ms * 1e-3) / 1e12,
                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     else:
-        roof = {"bound": "alu" if dom[0] == "gj_leaf" else "mfma",
+        # the GEMMs and the blocked leaf Gauss-Jordan (its panel updates,
+        # 94% of its flops per the SQ_INSTS_VALU_MFMA_MOPS_F64 counter) run on
+        # the matrix cores; the interface inversions on the vector ALU (same
+        # FP64 peak on MI355X)
+        roof = {"bound": "mfma" if dom[0] in ("gemm", "gj_leaf") else "alu",
                 "achieved": w_launch / (avg_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
