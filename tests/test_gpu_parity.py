@@ -106,13 +106,15 @@ def test_multiple_rhs(nrhs):
         assert relerr(u[r], uo) <= TOL, r
 
 
-@pytest.mark.parametrize("nrhs", [16, 20, 32])
-def test_many_rhs_matrix_core_path(nrhs):
-    """16 or more right-hand sides take the MFMA apply path: every column
-    agrees with the single-right-hand-side solve (the vector path) and two
-    of them with the oracle."""
+@pytest.mark.parametrize("nrhs,p,q", [(16, 12, 11), (20, 12, 11), (32, 12, 11), (16, 16, 15),
+                                      (40, 16, 15), (20, 16, 14)])
+def test_many_rhs_matrix_core_path(nrhs, p, q):
+    """16 or more right-hand sides take the MFMA apply path (32 per
+    workgroup: 20 and 40 leave a partial block): every column agrees with
+    the single-right-hand-side solve (the vector path) and two of them with
+    the oracle; p = 16 with q = 14 pads the leaf level's K = 4q + 196."""
     H = _lib()
-    p, q = 12, 11
+    print(f"many rhs: nrhs={nrhs} p={p} q={q}", flush=True)
     t = H.Tree(0, 1, 0, 1, 4, 4)
     ot = oracle.Tree.uniform(0, 1, 0, 1, 4, 4)
     sols = [W.FourierSolution(40 + r) for r in range(nrhs)]
