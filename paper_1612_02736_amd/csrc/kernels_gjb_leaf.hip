@@ -55,7 +55,7 @@ struct Shared {
   int pivrow[MI];              // pivot row of step k
   double sig[MI];              // 1 / pivot of step k
   int info;
-  int ready;                   // last published panel
+  int ready;                   // last published half-panel (2 q + h; the tail: 2 NS)
   int done[NS];                // last panel each wavefront has applied
   int tail_done;               // last panel applied to the tail
   int abort;                   // a wait ran out (never in a correct run)
@@ -282,8 +282,10 @@ __device__ __forceinline__ void sweep_strip(dbl4 (&acc)[16], int q, int lane, Sh
     for (int v = 0; v < 4; ++v) sl[(16 * t + 4 * v + g) * S + n] = acc[t][v];
   __builtin_amdgcn_wave_barrier();
   sweep_half(sl, 0, 16 * q, lane, sh);
+  post(sh.ready, 2 * q, lane);           // P0 is final: the others may apply L0
   apply_half(sl, 0, 8, 16 * q, lane, sh);
   sweep_half(sl, 8, 16 * q + 8, lane, sh);
+  post(sh.ready, 2 * q + 1, lane);
 #pragma unroll
   for (int t = 0; t < 16; ++t)
 #pragma unroll
@@ -342,11 +344,14 @@ __device__ __forceinline__ void update_half(dbl4 (&acc)[16], const double *sl, i
 
 // strip <- L1 (L0 strip) for panel q: each half-panel's rows R zeroed, then
 // + P W, the second half gathering its W after the first half's update.
+// The caller has waited for the first half (ready >= 2 q); the second half
+// is applied once it is published.
 __device__ __forceinline__ void update_strip16(dbl4 (&acc)[16], int q, int lane, double *wt,
-                                               const Shared &sh) {
+                                               Shared &sh) {
   const double *sl = sh.slot[q % NSLOT];
   gather_w<8>(acc, 16 * q, lane, wt, sh);
   update_half(acc, sl, 0, lane, wt);
+  wait_at_least(sh, sh.ready, 2 * q + 1);
   gather_w<8>(acc, 16 * q + 8, lane, wt, sh);
   update_half(acc, sl, 8, lane, wt);
 }
@@ -540,7 +545,6 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
   double *wt = sh.wt[w];
   if (w == 0) {
     sweep_strip(acc, 0, lane, sh);
-    post(sh.ready, 0, lane);
   } else if (d.Aie >= 0) {      // A_ci,ce for the leaf products, meanwhile
     double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
     for (int idx = tid - 64; idx < MI * me; idx += NT - 64) {
@@ -558,7 +562,7 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
       if (q == NS - 1) {
         wait_all_done(sh, NS - NSLOT);
         sweep_tail(lane, sh);
-        post(sh.ready, NS, lane);
+        post(sh.ready, 2 * NS, lane);
       }
       post(sh.tail_done, q, lane);
       // the strip is also in slot q % NSLOT until every wavefront has
@@ -572,7 +576,7 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
       post(sh.done[w], q, lane);
     } else {
       const bool owner = w == q + 1;
-      wait_at_least(sh, sh.ready, q);
+      wait_at_least(sh, sh.ready, 2 * q);
       if (owner) {
         __builtin_amdgcn_s_setprio(2);
       } else if (q + 1 < NS && ((w - q - 1) & 3) == 0) {
@@ -580,7 +584,7 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
         // SIMD w mod 4) leave it alone until its sweep is published: FP64
         // matrix-core and FP64 vector work on one SIMD slow each other
         // down.  They catch up while the next sweep runs on another SIMD.
-        wait_at_least(sh, sh.ready, q + 1);
+        wait_at_least(sh, sh.ready, 2 * q + 3);
       }
       update_strip16(acc, q, lane, wt, sh);
       post(sh.done[w], q, lane);
@@ -588,12 +592,11 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
         if (q + 1 >= NSLOT) wait_all_done(sh, q + 1 - NSLOT);
         else if (q + 1 == 1) wait_all_done(sh, -1);   // tables in slot 1 no longer read
         sweep_strip(acc, q + 1, lane, sh);
-        post(sh.ready, q + 1, lane);
         __builtin_amdgcn_s_setprio(0);
       }
     }
   }
-  wait_at_least(sh, sh.ready, NS);   // the tail panel
+  wait_at_least(sh, sh.ready, 2 * NS);   // the tail panel
   update_strip4(acc, lane, wt, sh);
   // F(k, r_j) = M(r_k, j); H(h, r_j) = -M(196 + h, j)
   double *F = (double *)bs.d[d.fbuf] + d.F;
