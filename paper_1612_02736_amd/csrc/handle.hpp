@@ -64,13 +64,14 @@ enum StepKind {
   S_GEMM, S_GJ_LEAF, S_GJ_MERGE, S_ZDIFF, S_PANEL, S_COLPERM, S_APPLY, S_COPY_F, S_VECOP
 };
 
+constexpr int kPanelLevel = -(1 << 30);
 struct Step {
   StepKind kind;
   int cls = 0;
   int64_t d0 = 0, nd = 0;   // descriptor range
   int64_t ntiles = 0;
   int maxm = 0;
-  int kb = 0;
+  int kb = 0;                 // PANEL: panel start, or kPanelLevel (one launch per level)
   int64_t fin0 = 0, nfin = 0;  // APPLY: finalize list range
   int64_t fin_maxm = 0;
   int64_t tmap0 = 0;          // GEMM / APPLY: start of the step's tile map

@@ -325,6 +325,13 @@ void emit_inverse_steps(const std::vector<MergeInvDesc> &lev, std::vector<MergeI
   Step z{S_ZDIFF};
   z.d0 = d0; z.nd = (int64_t)big.size(); z.maxm = bigmax;
   prog.push_back(z);
+  if (gj_level_fits(bigmax, (int)big.size())) {
+    // one launch for the level, strips resident
+    Step s{S_PANEL};
+    s.d0 = d0; s.nd = (int64_t)big.size(); s.kb = kPanelLevel; s.maxm = bigmax;
+    s.cls = gj_level_force_retire() ? 1 : 0;
+    prog.push_back(s);
+  } else
   // launch kb applies panel kb's update to the other columns and sweeps
   // panel kb + NB (kb = -NB: only the sweep of panel 0)
   for (int kb = -NBp; kb < bigmax; kb += NBp) {
@@ -541,8 +548,8 @@ static int plan_layout(PlanCtx &C) {
     const int m = (int)B.gi.size(), en = (int)B.nat.size(), ef = (int)B.fin.size();
     if (gj_merge_class(m) < 0) {
       Lo.W_scr[b] = scr_take(std::max<int64_t>(int64_t(kPanelNBMax) * m, int64_t(m) * m));
-      Lo.ipiv[b] = Lo.ipiv_n;          // pivrow[m], stepof[m]
-      Lo.ipiv_n += 2 * int64_t(m);
+      Lo.ipiv[b] = Lo.ipiv_n;          // pivrow[m], stepof[m], level control
+      Lo.ipiv_n += gj_int_scratch(m);
     }
     if (B.coarsened && B.parent >= 0) {
       Lo.Tn_scr[b] = scr_take(int64_t(en) * en);
@@ -1403,11 +1410,16 @@ static void annotate_work(std::vector<Step> &prog, const GemmList &gl,
         case S_GJ_MERGE: w += 2.0 * double(mv[i].m) * mv[i].m * mv[i].m; break;
         case S_PANEL: {
           // update by panel kb of the other columns, sweep of panel kb + NB
+          // (the level form: every kb)
           const int NBp = panel_nb(s.maxm), m = mv[i].m;
-          const double nu = s.kb >= 0 ? std::min(NBp, m - s.kb) : 0;
-          const double ns = std::min(NBp, m - (s.kb + NBp));
-          if (nu > 0) w += 2.0 * m * (m - nu) * nu;
-          if (ns > 0) w += 2.0 * m * ns * ns;
+          const int k_lo = s.kb == kPanelLevel ? -NBp : s.kb;
+          const int k_hi = s.kb == kPanelLevel ? m : s.kb + 1;
+          for (int kb = k_lo; kb < k_hi; kb += NBp) {
+            const double nu = kb >= 0 ? std::min(NBp, m - kb) : 0;
+            const double ns = std::min(NBp, m - (kb + NBp));
+            if (nu > 0) w += 2.0 * m * (m - nu) * nu;
+            if (ns > 0) w += 2.0 * m * ns * ns;
+          }
           break;
         }
         case S_APPLY:
@@ -1589,8 +1601,12 @@ int run_prog(hps_handle *H, std::vector<Step> &prog, Bases bs, int nrhs, int pre
         if (e == hipSuccess) e = launch_gj_ginit(H->d_minv.p + s.d0, (int)s.nd, s.maxm, H->ipiv.p, st);
         break;
       case S_PANEL:
-        e = launch_gj_panel(H->d_minv.p + s.d0, (int)s.nd, s.kb, s.maxm, bs, H->ipiv.p,
-                            H->info.p, st);
+        if (s.kb == kPanelLevel)
+          e = launch_gj_level(H->d_minv.p + s.d0, (int)s.nd, s.maxm, bs, H->ipiv.p, H->info.p,
+                              s.cls, st);
+        else
+          e = launch_gj_panel(H->d_minv.p + s.d0, (int)s.nd, s.kb, s.maxm, bs, H->ipiv.p,
+                              H->info.p, st);
         break;
       case S_COLPERM:
         e = launch_gj_colperm(H->d_minv.p + s.d0, (int)s.nd, s.maxm, bs, H->ipiv.p, H->psrc.p,
@@ -2019,7 +2035,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   HIPCHK(launch_fill(H.ws.p + nn * batch, 0.0, nn, st));
   const int64_t wsz = std::max<int64_t>(int64_t(kPanelNBMax) * n, nn);
   HIPCHK(H.scr.alloc(size_t(wsz) * batch + 64));
-  HIPCHK(H.ipiv.alloc(size_t(2 * n) * batch));
+  HIPCHK(H.ipiv.alloc(size_t(gj_int_scratch(n)) * batch));
   HIPCHK(H.psrc.alloc(size_t(n) * batch));
   HIPCHK(H.info.alloc(batch));
   HIPCHK(hipMemsetAsync(H.info.p, 0, sizeof(int32_t) * batch, st));
@@ -2027,7 +2043,7 @@ extern "C" int hps_debug_invert(int n, int batch, const double *A, double *X, vo
   for (int b = 0; b < batch; ++b) {
     MergeInvDesc d{};
     d.Ta = nn * b; d.Tb = nn * batch; d.lda = n; d.ldb = n; d.m = n; d.info = b;
-    d.X = nn * (batch + 1 + b); d.W = wsz * b; d.ipiv = int64_t(2 * n) * b;
+    d.X = nn * (batch + 1 + b); d.W = wsz * b; d.ipiv = gj_int_scratch(n) * b;
     lev.push_back(d);
   }
   GemmList gl;

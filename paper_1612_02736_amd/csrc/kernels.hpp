@@ -40,6 +40,17 @@ hipError_t launch_zdiff(const MergeInvDesc *descs, int nd, int maxm, const Bases
                         hipStream_t st);
 hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
                            const Bases &bs, int32_t *ipiv, int32_t *info, hipStream_t st);
+// int scratch of one blocked inversion of an m x m block: pivrow[m],
+// stepof[m], kGjLevelCtl control words of the level form (ready, ticket),
+// progress[strips of 16]
+constexpr int kGjLevelCtl = 32;
+inline int64_t gj_int_scratch(int m) { return 2 * int64_t(m) + kGjLevelCtl + (m + 15) / 16; }
+// One launch for the whole blocked inversion of a level, every strip resident
+// (only where gj_level_fits(maxm, nd) holds for the current device).
+bool gj_level_fits(int maxm, int nd);
+bool gj_level_force_retire();
+hipError_t launch_gj_level(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                           int32_t *ipiv, int32_t *info, int retire, hipStream_t st);
 hipError_t launch_gj_ginit(const MergeInvDesc *descs, int nd, int maxm, int32_t *g,
                            hipStream_t st);
 hipError_t launch_gj_colperm(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,

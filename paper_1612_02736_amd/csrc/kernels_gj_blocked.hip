@@ -1,5 +1,7 @@
 // Blocked Gauss-Jordan inversion of large interface blocks (m > 196) of the
 // merges (Sec. 4).
+#include <cstdlib>
+
 #include "gj_core.hpp"
 
 namespace hps {
@@ -22,10 +24,10 @@ __global__ __launch_bounds__(256) void zdiff_kernel(const MergeInvDesc *__restri
   }
 }
 
-// Blocked Gauss-Jordan with implicit partial pivoting (no row interchanges),
-// one launch per panel of NB columns.  The panel sweep is the textbook one
-// restricted to the panel's columns: the pivot row of column k is the unused
-// row of largest magnitude.  If R is the set of a panel's pivot rows and L the
+// Blocked Gauss-Jordan with implicit partial pivoting (no row interchanges)
+// over panels of NB columns.  The panel sweep is the textbook one restricted
+// to the panel's columns: the pivot row of column k is the unused row of
+// largest magnitude.  If R is the set of a panel's pivot rows and L the
 // product of its elementary sweep matrices, L differs from I only in the
 // columns R and the swept panel column c holds L(:, r_c); every other column
 // B therefore becomes L B = (B with rows R set to 0) + P W, with P the swept
@@ -34,27 +36,215 @@ __global__ __launch_bounds__(256) void zdiff_kernel(const MergeInvDesc *__restri
 // inverse.  pivrow[k] = r_k and stepof[r] = the step that used row r (-1
 // before) live in int scratch.
 //
-// Launch kb (kb < 0: the first) has one workgroup per strip of NB columns:
-// every strip other than panel kb applies panel kb's update (the strip is
-// held in registers, row t + NT i by thread t; the threads holding the rows R
-// copy them to LDS as W), and the strip of the next panel then sweeps its
-// columns in the same registers.  The sweep keeps pivot rows unscaled until
-// the pivot row itself is written (one multiply per row and column step).  So the next panel's
-// sweep follows its update without a launch in between, and only the
-// columns of a strip are written by the strip's own workgroup.
-//
-// The sweep takes one barrier per column: every wavefront's best candidate
-// row travels to LDS with its key, so after the barrier all threads read the
-// pivot row from the winning wavefront's slot.
+// One workgroup holds one strip of NB columns in registers (row t + NT i by
+// thread t).  Two drivers share the strip update and the sweep below: one
+// launch per panel (gj_step_kernel), or one launch per level in which every
+// strip stays in registers from the first panel to the last and the panels
+// pass through memory (gj_level_kernel).
+
+template <int NB, int NW>
+struct StripShared {
+  unsigned wkey[2][NW];
+  double crow[2][NW][NB];
+  __align__(16) double Wsh[NB][NB];
+  int rsh[NB];
+  int timeout;                 // gj_level_kernel: 1 a wait ran out, 2 retired
+  int strip;                   // gj_level_kernel: the strip taken
+};
+
+// pan <- (pan with rows R set to 0) + P W for the panel whose nbv swept
+// columns are P (column c at P + c n) and whose pivot rows are
+// piv[0 .. nbv - 1].  The threads holding the rows R copy them to LDS as W
+// first.  Returns the mask of this thread's register rows that are in R.
+template <int NB, int RPT, int NT>
+__device__ __forceinline__ unsigned strip_update(double (&pan)[RPT][NB], const double *P, int n,
+                                                 int nbv, const int32_t *piv,
+                                                 StripShared<NB, NT / 64> &sh) {
+  const int tid = threadIdx.x;
+  // my rows of the swept panel, loaded up front where registers allow
+  constexpr bool PRE = RPT <= 2;
+  double pr[PRE ? RPT : 1][NB];
+  if constexpr (PRE) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + NT * i;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        pr[i][c] = (row < n && c < nbv) ? P[row + int64_t(c) * n] : 0.0;
+    }
+  }
+  if (tid < NB) sh.rsh[tid] = tid < nbv ? piv[tid] : -1;
+  for (int e = tid; e < NB * NB; e += NT)
+    if (e / NB >= nbv) sh.Wsh[e / NB][e % NB] = 0.0;
+  __syncthreads();
+  // W = the strip's rows R (old values), from the threads that hold them
+  unsigned rmask = 0u;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = tid + NT * i;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (sh.rsh[c] == row) {
+        rmask |= 1u << i;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) sh.Wsh[c][j] = pan[i][j];
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i)
+    if ((rmask >> i) & 1u) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) pan[i][j] = 0.0;
+    }
+  if constexpr (PRE) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double2 *wr = reinterpret_cast<const double2 *>(&sh.Wsh[c][0]);
+#pragma unroll
+      for (int j2 = 0; j2 < NB / 2; ++j2) {
+        const double2 w = wr[j2];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          pan[i][2 * j2] = fma(pr[i][c], w.x, pan[i][2 * j2]);
+          pan[i][2 * j2 + 1] = fma(pr[i][c], w.y, pan[i][2 * j2 + 1]);
+        }
+      }
+      // one row of W in flight at a time (register pressure)
+      asm volatile("" ::: "memory");
+    }
+  } else {
+#pragma unroll 2
+    for (int c = 0; c < nbv; ++c) {
+      double pc[RPT];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = tid + NT * i;
+        pc[i] = row < n ? P[row + int64_t(c) * n] : 0.0;
+      }
+      const double2 *wr = reinterpret_cast<const double2 *>(&sh.Wsh[c][0]);
+#pragma unroll
+      for (int j2 = 0; j2 < NB / 2; ++j2) {
+        const double2 w = wr[j2];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          pan[i][2 * j2] = fma(pc[i], w.x, pan[i][2 * j2]);
+          pan[i][2 * j2 + 1] = fma(pc[i], w.y, pan[i][2 * j2 + 1]);
+        }
+      }
+    }
+  }
+  return rmask;
+}
+
+// Sweep of the nbv columns of the strip starting at column c0, umask holding
+// the register rows already used as pivots (or padding).  One barrier per
+// column: every wavefront's best candidate row travels to LDS with its key,
+// so after the barrier all threads read the pivot row from the winning
+// wavefront's slot.  Pivot rows are kept unscaled until the pivot row itself
+// is written (one multiply per row and column step).  Returns the first
+// failed step (+-(k + 1), as info reports it) or 0.
+template <int NB, int RPT, int NT>
+__device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &umask, int c0,
+                                           int nbv, int32_t *pivrow, int32_t *stepof,
+                                           StripShared<NB, NT / 64> &sh) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int first_bad = 0;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < nbv) {
+      const int par = c & 1;
+      unsigned key = 0;
+      int bi = 0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(pan[i][c], tid + NT * i);
+        if (k2 > key) { key = k2; bi = i; }
+      }
+      const unsigned wmax = wave_max_u32(key);
+      if (key == wmax && key != 0) {             // this wavefront's candidate row
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == bi) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) sh.crow[par][wid][cc] = pan[i][cc];
+          }
+      }
+      if (lane == 0) sh.wkey[par][wid] = wmax;
+      __syncthreads();
+      unsigned best = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) best = max(best, sh.wkey[par][w]);
+      // row r is held by thread r mod NT, so its candidate slot is that
+      // thread's wavefront
+      const int r = __builtin_amdgcn_readfirstlane(key_row(best));
+      const double *prow = sh.crow[par][(r % NT) >> 6];
+      if (tid == 0) {
+        pivrow[c0 + c] = r;
+        stepof[r] = c0 + c;
+      }
+      const double piv = prow[c];
+      const bool ok = (piv != 0.0) && isfinite(piv);
+      if (!ok && first_bad == 0) first_bad = isfinite(piv) ? (c0 + c + 1) : -(c0 + c + 1);
+      const double ip = ok ? recip_f64(piv) : 0.0;
+      double sr[NB];             // the pivot row, unscaled
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) sr[cc] = prow[cc];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const double f = pan[i][c] * ip;
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc)
+          if (cc != c) pan[i][cc] = fma(-f, sr[cc], pan[i][cc]);
+        pan[i][c] = -f;
+        if (tid + NT * i == r) {                 // the pivot row itself
+          umask |= 1u << i;
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) pan[i][cc] = cc == c ? ip : sr[cc] * ip;
+        }
+      }
+    }
+  }
+  return first_bad;
+}
+
+template <int NB, int RPT, int NT>
+__device__ __forceinline__ void strip_load(double (&pan)[RPT][NB], const double *src, int n,
+                                           int ncv) {
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = threadIdx.x + NT * i;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      pan[i][c] = (row < n && c < ncv) ? src[row + int64_t(c) * n] : 0.0;
+  }
+}
+
+template <int NB, int RPT, int NT>
+__device__ __forceinline__ void strip_store(const double (&pan)[RPT][NB], double *dst, int n,
+                                            int ncv) {
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = threadIdx.x + NT * i;
+    if (row < n) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < ncv) dst[row + int64_t(c) * n] = pan[i][c];
+    }
+  }
+}
+
+// Launch kb (kb < 0: the first) has one workgroup per strip: every strip
+// other than panel kb applies panel kb's update, and the strip of the next
+// panel then sweeps its columns in the same registers, so the next panel's
+// sweep follows its update without a launch in between and only the columns
+// of a strip are written by the strip's own workgroup.
 template <int NB, int RPT, int NT>
 __global__ __launch_bounds__(NT) void gj_step_kernel(
     const MergeInvDesc *__restrict__ descs, int nd, int kb, Bases bs,
     int32_t *__restrict__ g_all, int32_t *__restrict__ info) {
-  constexpr int NW = NT / 64;
-  __shared__ unsigned wkey[2][NW];
-  __shared__ double crow[2][NW][NB];
-  __shared__ __align__(16) double Wsh[NB][NB];
-  __shared__ int rsh[NB];
+  __shared__ StripShared<NB, NT / 64> sh;
   const MergeInvDesc &d = descs[blockIdx.y];
   const int n = d.m;
   const int c0 = int(blockIdx.x) * NB;
@@ -67,178 +257,173 @@ __global__ __launch_bounds__(NT) void gj_step_kernel(
   double *A = (double *)bs.d[BUF_WS] + d.X;
   int32_t *pivrow = g_all + d.ipiv;
   int32_t *stepof = pivrow + n;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double pan[RPT][NB];
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int row = tid + NT * i;
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-      pan[i][c] = (row < n && c < ncv) ? A[row + int64_t(c0 + c) * n] : 0.0;
-  }
-  if (kb >= 0) {
-    // update by panel kb: pan <- (pan with rows R set to 0) + P W
-    const int nbv = min(NB, n - kb);
-    const double *P = A + int64_t(kb) * n;
-    // my rows of the swept panel kb, loaded up front where registers allow
-    constexpr bool PRE = RPT <= 2;
-    double pr[PRE ? RPT : 1][NB];
-    if constexpr (PRE) {
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int row = tid + NT * i;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          pr[i][c] = (row < n && c < nbv) ? P[row + int64_t(c) * n] : 0.0;
-      }
-    }
-    if (tid < NB) rsh[tid] = tid < nbv ? pivrow[kb + tid] : -1;
-    for (int e = tid; e < NB * NB; e += NT)
-      if (e / NB >= nbv) Wsh[e / NB][e % NB] = 0.0;
-    __syncthreads();
-    // W = the strip's rows R (old values), from the threads that hold them
-    unsigned rmask = 0u;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int row = tid + NT * i;
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (rsh[c] == row) {
-          rmask |= 1u << i;
-#pragma unroll
-          for (int j = 0; j < NB; ++j) Wsh[c][j] = pan[i][j];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RPT; ++i)
-      if ((rmask >> i) & 1u) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) pan[i][j] = 0.0;
-      }
-    if constexpr (PRE) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const double2 *wr = reinterpret_cast<const double2 *>(&Wsh[c][0]);
-#pragma unroll
-        for (int j2 = 0; j2 < NB / 2; ++j2) {
-          const double2 w = wr[j2];
-#pragma unroll
-          for (int i = 0; i < RPT; ++i) {
-            pan[i][2 * j2] = fma(pr[i][c], w.x, pan[i][2 * j2]);
-            pan[i][2 * j2 + 1] = fma(pr[i][c], w.y, pan[i][2 * j2 + 1]);
-          }
-        }
-        // one row of W in flight at a time (register pressure)
-        asm volatile("" ::: "memory");
-      }
-    } else {
-#pragma unroll 2
-      for (int c = 0; c < nbv; ++c) {
-        double pc[RPT];
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const int row = tid + NT * i;
-          pc[i] = row < n ? P[row + int64_t(c) * n] : 0.0;
-        }
-        const double2 *wr = reinterpret_cast<const double2 *>(&Wsh[c][0]);
-#pragma unroll
-        for (int j2 = 0; j2 < NB / 2; ++j2) {
-          const double2 w = wr[j2];
-#pragma unroll
-          for (int i = 0; i < RPT; ++i) {
-            pan[i][2 * j2] = fma(pc[i], w.x, pan[i][2 * j2]);
-            pan[i][2 * j2 + 1] = fma(pc[i], w.y, pan[i][2 * j2 + 1]);
-          }
-        }
-      }
-    }
-  }
+  strip_load<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
+  if (kb >= 0)
+    (void)strip_update<NB, RPT, NT>(pan, A + int64_t(kb) * n, n, min(NB, n - kb), pivrow + kb,
+                                    sh);
   int first_bad = 0;
   if (sweep) {
-    const int nbv = ncv;
     unsigned umask = 0u;          // rows already used as pivots (or padding)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + NT * i;
+      const int row = threadIdx.x + NT * i;
       if (row >= n || stepof[row] >= 0) umask |= 1u << i;
     }
+    first_bad = strip_sweep<NB, RPT, NT>(pan, umask, c0, ncv, pivrow, stepof, sh);
+  }
+  strip_store<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
+  if (sweep && threadIdx.x == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
+}
+
+// One launch per level (gj_level_kernel, then gj_level_rest_kernel): every
+// strip stays in registers while the panels pass through memory.  A
+// workgroup takes the next strip of its matrix in order of arrival (a ticket
+// counter), applies panels 0 .. s - 1 as they are published, sweeps panel s
+// and publishes it (its swept columns into the scratch copy Y, its pivot rows
+// into pivrow, then the matrix's counter `ready` = s), and goes on applying
+// the later panels.  Waits before the sweep are on panels whose owners
+// arrived earlier, so they always end; after its sweep a workgroup waits for
+// panel q only while q's owner has arrived, and otherwise retires after
+// kRetireTicks (records in progress[s] the last panel applied and stores its
+// strip), so no workgroup ever waits on one that cannot be scheduled, whatever
+// else runs on the device.  gj_level_rest_kernel then applies the panels a
+// retired strip missed (none when the grid was resident throughout).  Every
+// wait is also bounded (2^20 polls), after which the matrix reports
+// kGjSyncTimeout through info.
+//
+// Ordering across workgroups (which may sit on different XCDs with their own
+// L2): each thread of the publishing workgroup issues an agent-scope release
+// fence after its stores, then a barrier, then one thread stores the counter
+// with release semantics; a waiting workgroup polls the counter with
+// agent-scope loads, meets at a barrier, and every thread issues an
+// agent-scope acquire fence before reading the panel.
+constexpr unsigned kLevelSpinLimit = 1u << 20;
+constexpr uint64_t kRetireTicks = 10000;      // 100 us of the 100 MHz real-time counter
+
+template <int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_level_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, Bases bs, int32_t *__restrict__ g_all,
+    int32_t *__restrict__ info, int retire_after_sweep) {
+  __shared__ StripShared<NB, NT / 64> sh;
+  const MergeInvDesc &d = descs[blockIdx.y];
+  const int n = d.m, np = (n + NB - 1) / NB;
+  if (int(blockIdx.x) >= np) return;
+  const int tid = threadIdx.x;
+  int32_t *pivrow = g_all + d.ipiv;
+  int32_t *stepof = pivrow + n;
+  int32_t *ready = pivrow + 2 * n, *ticket = ready + 1, *progress = ready + kGjLevelCtl;
+  if (tid == 0) {
+    sh.timeout = 0;
+    sh.strip = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const int s = __builtin_amdgcn_readfirstlane(sh.strip);
+  const int c0 = s * NB, ncv = min(NB, n - c0);
+  double *A = (double *)bs.d[BUF_WS] + d.X;
+  double *Y = (double *)bs.d[BUF_SCR] + d.W;     // published panels (n x n)
+  double pan[RPT][NB];
+  strip_load<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
+  unsigned umask = 0u;            // rows already used as pivots (or padding)
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c < nbv) {
-        const int par = c & 1;
-        unsigned key = 0;
-        int bi = 0;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(pan[i][c], tid + NT * i);
-          if (k2 > key) { key = k2; bi = i; }
-        }
-        const unsigned wmax = wave_max_u32(key);
-        if (key == wmax && key != 0) {             // this wavefront's candidate row
-#pragma unroll
-          for (int i = 0; i < RPT; ++i)
-            if (i == bi) {
-#pragma unroll
-              for (int cc = 0; cc < NB; ++cc) crow[par][wid][cc] = pan[i][cc];
-            }
-        }
-        if (lane == 0) wkey[par][wid] = wmax;
-        __syncthreads();
-        unsigned best = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) best = max(best, wkey[par][w]);
-        // row r is held by thread r mod NT, so its candidate slot is that
-        // thread's wavefront
-        const int r = __builtin_amdgcn_readfirstlane(key_row(best));
-        const double *prow = crow[par][(r % NT) >> 6];
-        if (tid == 0) {
-          pivrow[c0 + c] = r;
-          stepof[r] = c0 + c;
-        }
-        const double piv = prow[c];
-        const bool ok = (piv != 0.0) && isfinite(piv);
-        if (!ok && first_bad == 0) first_bad = isfinite(piv) ? (c0 + c + 1) : -(c0 + c + 1);
-        const double ip = ok ? recip_f64(piv) : 0.0;
-        double sr[NB];             // the pivot row, unscaled
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) sr[cc] = prow[cc];
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const double f = pan[i][c] * ip;
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc)
-            if (cc != c) pan[i][cc] = fma(-f, sr[cc], pan[i][cc]);
-          pan[i][c] = -f;
-          if (tid + NT * i == r) {                 // the pivot row itself
-            umask |= 1u << i;
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) pan[i][cc] = cc == c ? ip : sr[cc] * ip;
+  for (int i = 0; i < RPT; ++i)
+    if (tid + NT * i >= n) umask |= 1u << i;
+  // wait for panel q (retiring instead if q follows the sweep and its owner
+  // has not arrived); false: stop
+  auto wait_panel = [&](int q) -> bool {
+    if (tid == 0) {
+      uint64_t t0 = 0;
+      for (unsigned spins = 0;; ++spins) {
+        if (__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= q) break;
+        if (q > s && __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= q) {
+          const uint64_t t = __builtin_amdgcn_s_memrealtime();
+          if (t0 == 0) t0 = t;
+          else if (t - t0 > kRetireTicks) {
+            sh.timeout = 2;
+            break;
           }
         }
+        if (spins >= kLevelSpinLimit) {
+          sh.timeout = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
     }
+    __syncthreads();
+    if (sh.timeout) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+  };
+  int first_bad = 0, done_to = -1;
+  bool go = true;
+  for (int q = 0; q < s; ++q) {
+    if (!(go = wait_panel(q))) break;
+    umask |= strip_update<NB, RPT, NT>(pan, Y + int64_t(q) * NB * n, n, NB, pivrow + q * NB, sh);
+    done_to = q;
   }
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int row = tid + NT * i;
-    if (row < n) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < ncv) A[row + int64_t(c0 + c) * n] = pan[i][c];
+  if (go) {
+    first_bad = strip_sweep<NB, RPT, NT>(pan, umask, c0, ncv, pivrow, stepof, sh);
+    strip_store<NB, RPT, NT>(pan, Y + int64_t(c0) * n, n, ncv);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(ready, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    done_to = s;
+    for (int q = s + 1; q < np && !retire_after_sweep; ++q) {
+      if (!wait_panel(q)) break;
+      (void)strip_update<NB, RPT, NT>(pan, Y + int64_t(q) * NB * n, n, min(NB, n - q * NB),
+                                      pivrow + q * NB, sh);
+      done_to = q;
     }
   }
-  if (sweep && tid == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
+  strip_store<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
+  if (tid == 0) {
+    progress[s] = done_to;
+    if (sh.timeout == 1) info[d.info] = kGjSyncTimeout;
+    else if (first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
+  }
+}
+
+// The panels after progress[s] that a retired strip s did not apply (all
+// published by now).
+template <int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_level_rest_kernel(
+    const MergeInvDesc *__restrict__ descs, int nd, Bases bs, int32_t *__restrict__ g_all) {
+  __shared__ StripShared<NB, NT / 64> sh;
+  const MergeInvDesc &d = descs[blockIdx.y];
+  const int n = d.m, np = (n + NB - 1) / NB;
+  const int s = blockIdx.x;
+  if (s >= np) return;
+  const int32_t *pivrow = g_all + d.ipiv;
+  const int32_t *progress = pivrow + 2 * n + kGjLevelCtl;
+  const int q0 = progress[s] + 1;
+  if (q0 >= np) return;
+  const int c0 = s * NB, ncv = min(NB, n - c0);
+  double *A = (double *)bs.d[BUF_WS] + d.X;
+  const double *Y = (const double *)bs.d[BUF_SCR] + d.W;
+  double pan[RPT][NB];
+  strip_load<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
+  for (int q = q0; q < np; ++q) {
+    if (q == s) continue;
+    (void)strip_update<NB, RPT, NT>(pan, Y + int64_t(q) * NB * n, n, min(NB, n - q * NB),
+                                    pivrow + q * NB, sh);
+    __syncthreads();            // W of this panel read by every thread
+  }
+  strip_store<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
 }
 
 // stepof = -1 before the first panel; pivrow[k] = k (in range even if a
-// failed build leaves a step without a pivot)
+// failed build leaves a step without a pivot); no panel published yet
 __global__ __launch_bounds__(256) void gj_ginit_kernel(const MergeInvDesc *__restrict__ descs,
                                                        int nd, int32_t *__restrict__ g_all) {
   const MergeInvDesc &d = descs[blockIdx.y];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += gridDim.x * blockDim.x) {
     g_all[d.ipiv + i] = i;
     g_all[d.ipiv + d.m + i] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {   // gj_level_kernel: ready, ticket
+    g_all[d.ipiv + 2 * d.m] = -1;
+    g_all[d.ipiv + 2 * d.m + 1] = 0;
   }
 }
 
@@ -298,6 +483,64 @@ hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// The level form (matrices of up to 1024 rows: larger ones need more rows per
+// thread than the registers hold next to a resident strip).
+static const void *level_kernel_for(int maxm, int &nt) {
+  constexpr int NB = 16;
+  if (maxm <= 256) { nt = 256; return (const void *)gj_level_kernel<NB, 1, 256>; }
+  if (maxm <= 512) { nt = 512; return (const void *)gj_level_kernel<NB, 1, 512>; }
+  if (maxm <= 1024) { nt = 512; return (const void *)gj_level_kernel<NB, 2, 512>; }
+  nt = 0;
+  return nullptr;
+}
+
+// The level form is chosen where its grid (strips x matrices) is resident at
+// once on the current device (otherwise strips would retire and leave their
+// work to gj_level_rest_kernel).  HPS_GJ_LEVEL=0 selects the per-panel form.
+bool gj_level_fits(int maxm, int nd) {
+  const char *e = std::getenv("HPS_GJ_LEVEL");
+  if (e && e[0] == '0') return false;
+  int nt = 0;
+  const void *k = level_kernel_for(maxm, nt);
+  if (!k || nd <= 0) return false;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nt, 0) != hipSuccess) return false;
+  const int64_t grid = int64_t((maxm + 15) / 16) * nd;
+  return grid <= int64_t(per_cu) * cus;
+}
+
+template <int RPT, int NT>
+static hipError_t level_launch(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                               int32_t *g, int32_t *info, int retire, hipStream_t st) {
+  constexpr int NB = 16;
+  const dim3 grid(unsigned((maxm + NB - 1) / NB), unsigned(nd));
+  hipLaunchKernelGGL((gj_level_kernel<NB, RPT, NT>), grid, dim3(NT), 0, st, descs, nd, bs, g,
+                     info, retire);
+  hipLaunchKernelGGL((gj_level_rest_kernel<NB, RPT, NT>), grid, dim3(NT), 0, st, descs, nd, bs,
+                     g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_level(const MergeInvDesc *descs, int nd, int maxm, const Bases &bs,
+                           int32_t *g, int32_t *info, int retire, hipStream_t st) {
+  if (nd <= 0) return hipSuccess;
+  if (maxm <= 256) return level_launch<1, 256>(descs, nd, maxm, bs, g, info, retire, st);
+  if (maxm <= 512) return level_launch<1, 512>(descs, nd, maxm, bs, g, info, retire, st);
+  if (maxm <= 1024) return level_launch<2, 512>(descs, nd, maxm, bs, g, info, retire, st);
+  return hipErrorInvalidValue;
+}
+
+// HPS_GJ_LEVEL=2: every strip of the level form retires right after its
+// sweep, so gj_level_rest_kernel applies all later panels (same results;
+// exercises the remainder path).
+bool gj_level_force_retire() {
+  const char *e = std::getenv("HPS_GJ_LEVEL");
+  return e && e[0] == '2';
 }
 
 hipError_t launch_gj_ginit(const MergeInvDesc *descs, int nd, int maxm, int32_t *g,

@@ -118,6 +118,30 @@ def test_inverse_needs_pivoting(n):
         assert relerr(X[b], ref) < 1e-12
 
 
+@pytest.mark.parametrize("n", [197, 240, 500, 960])
+def test_inverse_level_form_matches_panel_form(n, monkeypatch):
+    """The blocked inversion in one launch per level (strips resident in
+    registers, panels passed through memory), the same with every strip
+    retiring after its own sweep (the remainder kernel applies the later
+    panels), and one launch per panel: bitwise the same inverse, since every
+    strip receives the same panel updates in the same order."""
+    import torch
+    from paper_1612_02736_amd.hps import debug_invert
+    rng = np.random.default_rng(2000 + n)
+    A = rng.standard_normal((2, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)
+    Ad = torch.from_numpy(A).cuda()
+    out = {}
+    for form in ("1", "2", "0"):
+        monkeypatch.setenv("HPS_GJ_LEVEL", form)
+        print(f"invert n={n} form {form}", flush=True)
+        out[form] = debug_invert(Ad)
+    assert torch.equal(out["1"], out["0"])
+    assert torch.equal(out["2"], out["0"])
+    X = out["1"].cpu().numpy()
+    for b in range(2):
+        assert relerr(X[b], np.linalg.inv(A[b])) < 1e-12
+
+
 def _build_pair(nx, ny, p, q=None, refine=None, coef=W.varcoeff):
     H = _H()
     q = q or p - 1
