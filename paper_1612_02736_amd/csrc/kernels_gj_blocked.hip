@@ -42,39 +42,77 @@ __global__ __launch_bounds__(256) void zdiff_kernel(const MergeInvDesc *__restri
 // strip stays in registers from the first panel to the last and the panels
 // pass through memory (gj_level_kernel).
 
+// Loads and stores of panels passed between workgroups inside one launch of
+// the level form carry the sc1 cache-policy bit (the bit agent-scope atomics
+// use), which keeps them coherent across the XCDs' L2 caches without a
+// cache-wide write-back or invalidation.  Panel columns go through buffer
+// instructions over the panel (num_records bytes): an offset past the end
+// loads 0 and drops a store, so inactive rows and columns need no branch.  Single words
+// (pivot rows, counters) are agent-scope relaxed atomics.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufSc1 = 16;               // cache policy: sc1
+constexpr unsigned kBufOut = 0x7ffffff0u; // an offset past every panel
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const double *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double coherent_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kBufSc1));
+}
+__device__ __forceinline__ void coherent_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kBufSc1);
+}
+__device__ __forceinline__ void coherent_store(__amdgpu_buffer_rsrc_t r, unsigned off, int32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, kBufSc1);
+}
+__device__ __forceinline__ int32_t coherent_load(const int32_t *p) {
+  return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int NB, int NW>
 struct StripShared {
   unsigned wkey[2][NW];
   double crow[2][NW][NB];
   __align__(16) double Wsh[NB][NB];
   int rsh[NB];
+  int pivl[NB];                // pivot rows of the strip's sweep
   int timeout;                 // gj_level_kernel: 1 a wait ran out, 2 retired
   int strip;                   // gj_level_kernel: the strip taken
 };
 
-// pan <- (pan with rows R set to 0) + P W for the panel whose nbv swept
-// columns are P (column c at P + c n) and whose pivot rows are
-// piv[0 .. nbv - 1].  The threads holding the rows R copy them to LDS as W
-// first.  Returns the mask of this thread's register rows that are in R.
-template <int NB, int RPT, int NT>
+// pan <- (pan with rows R set to 0) + P W for a panel of nbv <= K swept
+// columns P (column c at P + c n) whose pivot rows are piv[0 .. nbv - 1].  The
+// threads holding the rows R copy them to LDS as W first.  Returns the mask
+// of this thread's register rows that are in R.  COHERENT: P and piv were
+// published by another workgroup of this launch.
+template <int NB, int K, int RPT, int NT, bool COHERENT = false>
 __device__ __forceinline__ unsigned strip_update(double (&pan)[RPT][NB], const double *P, int n,
                                                  int nbv, const int32_t *piv,
                                                  StripShared<NB, NT / 64> &sh) {
   const int tid = threadIdx.x;
+  const __amdgpu_buffer_rsrc_t rs = panel_rsrc(P, COHERENT ? nbv * n * 8 : 0);
+  // entry (row, c) of the panel, 0 outside it
+  auto ldP = [&](int row, int c) -> double {
+    if constexpr (COHERENT)
+      return coherent_load(rs, row < n ? unsigned(row + c * n) * 8u : kBufOut);
+    else
+      return (row < n && c < nbv) ? P[row + int64_t(c) * n] : 0.0;
+  };
   // my rows of the swept panel, loaded up front where registers allow
   constexpr bool PRE = RPT <= 2;
-  double pr[PRE ? RPT : 1][NB];
+  double pr[PRE ? RPT : 1][K];
   if constexpr (PRE) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int row = tid + NT * i;
 #pragma unroll
-      for (int c = 0; c < NB; ++c)
-        pr[i][c] = (row < n && c < nbv) ? P[row + int64_t(c) * n] : 0.0;
+      for (int c = 0; c < K; ++c) pr[i][c] = ldP(row, c);
     }
   }
-  if (tid < NB) sh.rsh[tid] = tid < nbv ? piv[tid] : -1;
-  for (int e = tid; e < NB * NB; e += NT)
+  if (tid < K) sh.rsh[tid] = tid < nbv ? (COHERENT ? coherent_load(piv + tid) : piv[tid]) : -1;
+  for (int e = tid; e < K * NB; e += NT)
     if (e / NB >= nbv) sh.Wsh[e / NB][e % NB] = 0.0;
   __syncthreads();
   // W = the strip's rows R (old values), from the threads that hold them
@@ -83,7 +121,7 @@ __device__ __forceinline__ unsigned strip_update(double (&pan)[RPT][NB], const d
   for (int i = 0; i < RPT; ++i) {
     const int row = tid + NT * i;
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
+    for (int c = 0; c < K; ++c)
       if (sh.rsh[c] == row) {
         rmask |= 1u << i;
 #pragma unroll
@@ -99,7 +137,7 @@ __device__ __forceinline__ unsigned strip_update(double (&pan)[RPT][NB], const d
     }
   if constexpr (PRE) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
+    for (int c = 0; c < K; ++c) {
       const double2 *wr = reinterpret_cast<const double2 *>(&sh.Wsh[c][0]);
 #pragma unroll
       for (int j2 = 0; j2 < NB / 2; ++j2) {
@@ -118,10 +156,7 @@ __device__ __forceinline__ unsigned strip_update(double (&pan)[RPT][NB], const d
     for (int c = 0; c < nbv; ++c) {
       double pc[RPT];
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int row = tid + NT * i;
-        pc[i] = row < n ? P[row + int64_t(c) * n] : 0.0;
-      }
+      for (int i = 0; i < RPT; ++i) pc[i] = ldP(tid + NT * i, c);
       const double2 *wr = reinterpret_cast<const double2 *>(&sh.Wsh[c][0]);
 #pragma unroll
       for (int j2 = 0; j2 < NB / 2; ++j2) {
@@ -137,23 +172,80 @@ __device__ __forceinline__ unsigned strip_update(double (&pan)[RPT][NB], const d
   return rmask;
 }
 
+// Half h of panel q of the level form (columns 8 h .. 8 h + 7 of the panel in
+// Y, as published): L0 for h = 0, L1 for h = 1.
+template <int NB, int RPT, int NT, bool COHERENT>
+__device__ __forceinline__ unsigned strip_half_update(double (&pan)[RPT][NB], const double *Y,
+                                                      int n, int q, int h, const int32_t *pivrow,
+                                                      StripShared<NB, NT / 64> &sh) {
+  constexpr int H = NB / 2;
+  const int k0 = q * NB + h * H;
+  return strip_update<NB, H, RPT, NT, COHERENT>(pan, Y + int64_t(k0) * n, n, min(H, n - k0),
+                                                pivrow + k0, sh);
+}
+
+// Where the level form publishes a strip's panel: its swept columns into the
+// scratch copy Y, its pivot rows into pivrow / stepof, and the matrix's
+// counter `ready` in half-panels (2 s: columns 0..7 of panel s, 2 s + 1: all).
+struct PanelOut {
+  double *Y;
+  int32_t *ipiv;               // pivrow[n], then stepof[n]
+  int32_t *ready;
+  int n, s;
+};
+
+// Columns cfrom .. cto - 1 of the strip (starting at column c0) and their
+// pivot rows, with sc1 stores; the caller waits for them before signalling.
+template <int NB, int RPT, int NT>
+__device__ __forceinline__ void publish_half(const double (&pan)[RPT][NB], const PanelOut &o,
+                                             int c0, int cfrom, int cto,
+                                             const StripShared<NB, NT / 64> &sh) {
+  const __amdgpu_buffer_rsrc_t rs = panel_rsrc(o.Y + int64_t(c0) * o.n, NB * o.n * 8);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = threadIdx.x + NT * i;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      coherent_store(rs, (row < o.n && c >= cfrom && c < cto) ? unsigned(row + c * o.n) * 8u
+                                                               : kBufOut,
+                     pan[i][c]);
+  }
+  // pivot rows (threads of wavefront 0, which also wrote sh.pivl)
+  const int t = threadIdx.x, c = cfrom + t;
+  if (t < NB) {
+    const bool on = c < cto;
+    const int r = on ? sh.pivl[c] : 0;
+    const __amdgpu_buffer_rsrc_t ri =
+        __builtin_amdgcn_make_buffer_rsrc(o.ipiv, 0, 8 * o.n, 0x00020000);
+    coherent_store(ri, on ? unsigned(c0 + c) * 4u : kBufOut, r);
+    coherent_store(ri, on ? unsigned(o.n + r) * 4u : kBufOut, c0 + c);
+  }
+}
+
 // Sweep of the nbv columns of the strip starting at column c0, umask holding
 // the register rows already used as pivots (or padding).  One barrier per
 // column: every wavefront's best candidate row travels to LDS with its key,
 // so after the barrier all threads read the pivot row from the winning
 // wavefront's slot.  Pivot rows are kept unscaled until the pivot row itself
-// is written (one multiply per row and column step).  Returns the first
-// failed step (+-(k + 1), as info reports it) or 0.
-template <int NB, int RPT, int NT>
+// is written (one multiply per row and column step).  The pivot rows are
+// left in sh.pivl.  With PUB (the level form) the sweep publishes its first
+// 8 columns as they stand after step 7 (stores issued before step 8, the
+// counter raised after step 10 once they are complete), and the rest after
+// the last step.  Returns the first failed step (+-(k + 1), as info reports
+// it) or 0.
+template <int NB, int RPT, int NT, bool PUB = false>
 __device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &umask, int c0,
-                                           int nbv, int32_t *pivrow, int32_t *stepof,
-                                           StripShared<NB, NT / 64> &sh) {
+                                           int nbv, StripShared<NB, NT / 64> &sh,
+                                           const PanelOut *out = nullptr) {
   constexpr int NW = NT / 64;
+  constexpr int H = NB / 2;        // columns of the first published half
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int first_bad = 0;
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c < nbv) {
+      if constexpr (PUB)
+        if (c == H) publish_half<NB, RPT, NT>(pan, *out, c0, 0, H, sh);
       const int par = c & 1;
       unsigned key = 0;
       int bi = 0;
@@ -172,7 +264,11 @@ __device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &uma
           }
       }
       if (lane == 0) sh.wkey[par][wid] = wmax;
+      if constexpr (PUB)
+        if (c == H + 2) __builtin_amdgcn_s_waitcnt(0);   // the first half's stores
       __syncthreads();
+      if constexpr (PUB)
+        if (c == H + 2 && tid == 0) coherent_store(out->ready, 2 * out->s);
       unsigned best = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) best = max(best, sh.wkey[par][w]);
@@ -180,10 +276,7 @@ __device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &uma
       // thread's wavefront
       const int r = __builtin_amdgcn_readfirstlane(key_row(best));
       const double *prow = sh.crow[par][(r % NT) >> 6];
-      if (tid == 0) {
-        pivrow[c0 + c] = r;
-        stepof[r] = c0 + c;
-      }
+      if (tid == 0) sh.pivl[c] = r;
       const double piv = prow[c];
       const bool ok = (piv != 0.0) && isfinite(piv);
       if (!ok && first_bad == 0) first_bad = isfinite(piv) ? (c0 + c + 1) : -(c0 + c + 1);
@@ -205,6 +298,14 @@ __device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &uma
         }
       }
     }
+  }
+  __syncthreads();
+  if constexpr (PUB) {
+    // the second half (or the whole panel when it has at most H columns)
+    publish_half<NB, RPT, NT>(pan, *out, c0, nbv > H ? H : 0, nbv, sh);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) coherent_store(out->ready, 2 * out->s + 1);
   }
   return first_bad;
 }
@@ -260,8 +361,8 @@ __global__ __launch_bounds__(NT) void gj_step_kernel(
   double pan[RPT][NB];
   strip_load<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
   if (kb >= 0)
-    (void)strip_update<NB, RPT, NT>(pan, A + int64_t(kb) * n, n, min(NB, n - kb), pivrow + kb,
-                                    sh);
+    (void)strip_update<NB, NB, RPT, NT>(pan, A + int64_t(kb) * n, n, min(NB, n - kb),
+                                        pivrow + kb, sh);
   int first_bad = 0;
   if (sweep) {
     unsigned umask = 0u;          // rows already used as pivots (or padding)
@@ -270,7 +371,12 @@ __global__ __launch_bounds__(NT) void gj_step_kernel(
       const int row = threadIdx.x + NT * i;
       if (row >= n || stepof[row] >= 0) umask |= 1u << i;
     }
-    first_bad = strip_sweep<NB, RPT, NT>(pan, umask, c0, ncv, pivrow, stepof, sh);
+    first_bad = strip_sweep<NB, RPT, NT>(pan, umask, c0, ncv, sh);
+    if (threadIdx.x < ncv) {
+      const int r = sh.pivl[threadIdx.x];
+      pivrow[c0 + threadIdx.x] = r;
+      stepof[r] = c0 + threadIdx.x;
+    }
   }
   strip_store<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
   if (sweep && threadIdx.x == 0 && first_bad != 0 && info[d.info] == 0) info[d.info] = first_bad;
@@ -280,24 +386,29 @@ __global__ __launch_bounds__(NT) void gj_step_kernel(
 // strip stays in registers while the panels pass through memory.  A
 // workgroup takes the next strip of its matrix in order of arrival (a ticket
 // counter), applies panels 0 .. s - 1 as they are published, sweeps panel s
-// and publishes it (its swept columns into the scratch copy Y, its pivot rows
-// into pivrow, then the matrix's counter `ready` = s), and goes on applying
-// the later panels.  Waits before the sweep are on panels whose owners
-// arrived earlier, so they always end; after its sweep a workgroup waits for
-// panel q only while q's owner has arrived, and otherwise retires after
-// kRetireTicks (records in progress[s] the last panel applied and stores its
-// strip), so no workgroup ever waits on one that cannot be scheduled, whatever
-// else runs on the device.  gj_level_rest_kernel then applies the panels a
-// retired strip missed (none when the grid was resident throughout).  Every
-// wait is also bounded (2^20 polls), after which the matrix reports
-// kGjSyncTimeout through info.
+// and publishes it in two halves (strip_sweep), and goes on applying the
+// later panels.  A panel is applied as two rank-8 updates, its first 8
+// columns as they stood after the first 8 steps (L0) and then the rest (L1),
+// so a strip applies L0 of panel q while q's owner still sweeps its second
+// half, and only L1 separates the end of one sweep from the start of the
+// next.  Waits before the sweep are on panels whose owners arrived earlier,
+// so they always end; after its sweep a workgroup waits for panel q only
+// while q's owner has arrived, and otherwise retires after kRetireTicks
+// (records in progress[s] the last panel applied and stores its strip), so no
+// workgroup ever waits on one that cannot be scheduled, whatever else runs on
+// the device.  gj_level_rest_kernel then applies the panels a retired strip
+// missed (none when the grid was resident throughout).  Every wait is also
+// bounded (2^20 polls), after which the matrix reports kGjSyncTimeout through
+// info.
 //
 // Ordering across workgroups (which may sit on different XCDs with their own
-// L2): each thread of the publishing workgroup issues an agent-scope release
-// fence after its stores, then a barrier, then one thread stores the counter
-// with release semantics; a waiting workgroup polls the counter with
-// agent-scope loads, meets at a barrier, and every thread issues an
-// agent-scope acquire fence before reading the panel.
+// L2): the panel, its pivot rows and the counter are written and read with
+// sc1 accesses, coherent at agent scope without a cache-wide write-back or
+// invalidation.  The publishing workgroup waits for all its stores to
+// complete (s_waitcnt on every thread), meets at a barrier, then one thread
+// stores the counter; a waiting workgroup polls the counter with one thread,
+// meets at a barrier, and only then loads the panel, so every load is issued
+// after the counter was seen.
 constexpr unsigned kLevelSpinLimit = 1u << 20;
 constexpr uint64_t kRetireTicks = 10000;      // 100 us of the 100 MHz real-time counter
 
@@ -328,14 +439,15 @@ __global__ __launch_bounds__(NT) void gj_level_kernel(
 #pragma unroll
   for (int i = 0; i < RPT; ++i)
     if (tid + NT * i >= n) umask |= 1u << i;
-  // wait for panel q (retiring instead if q follows the sweep and its owner
-  // has not arrived); false: stop
-  auto wait_panel = [&](int q) -> bool {
+  // wait for half-panel h of panel h / 2 (retiring instead if that panel
+  // follows the sweep and its owner has not arrived); false: stop
+  auto wait_half = [&](int h, bool may_retire) -> bool {
+    const int q = h >> 1;
     if (tid == 0) {
       uint64_t t0 = 0;
       for (unsigned spins = 0;; ++spins) {
-        if (__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= q) break;
-        if (q > s && __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= q) {
+        if (coherent_load(ready) >= h) break;
+        if (may_retire && coherent_load(ticket) <= q) {
           const uint64_t t = __builtin_amdgcn_s_memrealtime();
           if (t0 == 0) t0 = t;
           else if (t - t0 > kRetireTicks) {
@@ -351,28 +463,27 @@ __global__ __launch_bounds__(NT) void gj_level_kernel(
       }
     }
     __syncthreads();
-    if (sh.timeout) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
+    return sh.timeout == 0;
   };
+  constexpr int H = NB / 2;
   int first_bad = 0, done_to = -1;
   bool go = true;
-  for (int q = 0; q < s; ++q) {
-    if (!(go = wait_panel(q))) break;
-    umask |= strip_update<NB, RPT, NT>(pan, Y + int64_t(q) * NB * n, n, NB, pivrow + q * NB, sh);
-    done_to = q;
+  for (int h = 0; h < 2 * s; ++h) {             // the halves of the full panels before s
+    if (!(go = wait_half(h, false))) break;
+    umask |= strip_half_update<NB, RPT, NT, true>(pan, Y, n, h >> 1, h & 1, pivrow, sh);
+    done_to = (h - 1) >> 1;
   }
   if (go) {
-    first_bad = strip_sweep<NB, RPT, NT>(pan, umask, c0, ncv, pivrow, stepof, sh);
-    strip_store<NB, RPT, NT>(pan, Y + int64_t(c0) * n, n, ncv);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(ready, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const PanelOut out{Y, pivrow, ready, n, s};
+    first_bad = strip_sweep<NB, RPT, NT, true>(pan, umask, c0, ncv, sh, &out);
     done_to = s;
     for (int q = s + 1; q < np && !retire_after_sweep; ++q) {
-      if (!wait_panel(q)) break;
-      (void)strip_update<NB, RPT, NT>(pan, Y + int64_t(q) * NB * n, n, min(NB, n - q * NB),
-                                      pivrow + q * NB, sh);
+      if (!wait_half(2 * q, true)) break;
+      (void)strip_half_update<NB, RPT, NT, true>(pan, Y, n, q, 0, pivrow, sh);
+      if (n - q * NB > H) {
+        if (!wait_half(2 * q + 1, false)) break;
+        (void)strip_half_update<NB, RPT, NT, true>(pan, Y, n, q, 1, pivrow, sh);
+      }
       done_to = q;
     }
   }
@@ -405,9 +516,13 @@ __global__ __launch_bounds__(NT) void gj_level_rest_kernel(
   strip_load<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
   for (int q = q0; q < np; ++q) {
     if (q == s) continue;
-    (void)strip_update<NB, RPT, NT>(pan, Y + int64_t(q) * NB * n, n, min(NB, n - q * NB),
-                                    pivrow + q * NB, sh);
-    __syncthreads();            // W of this panel read by every thread
+    // the two halves in the order of the level kernel
+    (void)strip_half_update<NB, RPT, NT, false>(pan, Y, n, q, 0, pivrow, sh);
+    __syncthreads();            // W of this half read by every thread
+    if (n - q * NB > NB / 2) {
+      (void)strip_half_update<NB, RPT, NT, false>(pan, Y, n, q, 1, pivrow, sh);
+      __syncthreads();
+    }
   }
   strip_store<NB, RPT, NT>(pan, A + int64_t(c0) * n, n, ncv);
 }
