@@ -241,20 +241,28 @@ __device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &uma
   constexpr int H = NB / 2;        // columns of the first published half
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int first_bad = 0;
+  // this thread's candidate row for column c (key, register row bi) and the
+  // wavefront's maximum key; step c computes them for column c + 1 right
+  // after updating that column, so the reduction overlaps the other updates
+  unsigned key = 0, wmax = 0;
+  int bi = 0;
+  auto search = [&](int c) {
+    key = 0;
+    bi = 0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(pan[i][c], tid + NT * i);
+      if (k2 > key) { key = k2; bi = i; }
+    }
+    wmax = wave_max_u32(key);
+  };
+  if (nbv > 0) search(0);
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c < nbv) {
       if constexpr (PUB)
         if (c == H) publish_half<NB, RPT, NT>(pan, *out, c0, 0, H, sh);
       const int par = c & 1;
-      unsigned key = 0;
-      int bi = 0;
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const unsigned k2 = ((umask >> i) & 1u) ? 0u : pivot_key(pan[i][c], tid + NT * i);
-        if (k2 > key) { key = k2; bi = i; }
-      }
-      const unsigned wmax = wave_max_u32(key);
       if (key == wmax && key != 0) {             // this wavefront's candidate row
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
@@ -284,18 +292,36 @@ __device__ __forceinline__ int strip_sweep(double (&pan)[RPT][NB], unsigned &uma
       double sr[NB];             // the pivot row, unscaled
 #pragma unroll
       for (int cc = 0; cc < NB; ++cc) sr[cc] = prow[cc];
+      double f[RPT];
+      unsigned isr = 0u;         // register rows that are the pivot row
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const double f = pan[i][c] * ip;
+        f[i] = pan[i][c] * ip;
+        if (tid + NT * i == r) isr |= 1u << i;
+      }
+      umask |= isr;
+      if (c + 1 < NB) {
+        // the next pivot column first, then its candidate search (the pivot
+        // row, fixed below, is already excluded through umask)
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) pan[i][c + 1] = fma(-f[i], sr[c + 1], pan[i][c + 1]);
+        if (c + 1 < nbv) search(c + 1);
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc)
-          if (cc != c) pan[i][cc] = fma(-f, sr[cc], pan[i][cc]);
-        pan[i][c] = -f;
-        if (tid + NT * i == r) {                 // the pivot row itself
-          umask |= 1u << i;
+          if (cc != c && cc != c + 1) pan[i][cc] = fma(-f[i], sr[cc], pan[i][cc]);
+        pan[i][c] = -f[i];
+      }
+      // the pivot row itself, in the one wavefront that holds it
+      if (((r % NT) >> 6) == wid) {
 #pragma unroll
-          for (int cc = 0; cc < NB; ++cc) pan[i][cc] = cc == c ? ip : sr[cc] * ip;
-        }
+        for (int i = 0; i < RPT; ++i)
+          if ((isr >> i) & 1u) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) pan[i][cc] = cc == c ? ip : sr[cc] * ip;
+          }
       }
     }
   }
@@ -600,13 +626,14 @@ hipError_t launch_gj_panel(const MergeInvDesc *descs, int nd, int kb, int maxm,
   return hipGetLastError();
 }
 
-// The level form (matrices of up to 1024 rows: larger ones need more rows per
-// thread than the registers hold next to a resident strip).
+// The level form (matrices of up to 1024 rows, one row per thread: larger
+// ones need more rows per thread than the registers hold next to a resident
+// strip).
 static const void *level_kernel_for(int maxm, int &nt) {
   constexpr int NB = 16;
   if (maxm <= 256) { nt = 256; return (const void *)gj_level_kernel<NB, 1, 256>; }
   if (maxm <= 512) { nt = 512; return (const void *)gj_level_kernel<NB, 1, 512>; }
-  if (maxm <= 1024) { nt = 512; return (const void *)gj_level_kernel<NB, 2, 512>; }
+  if (maxm <= 1024) { nt = 1024; return (const void *)gj_level_kernel<NB, 1, 1024>; }
   nt = 0;
   return nullptr;
 }
@@ -646,7 +673,7 @@ hipError_t launch_gj_level(const MergeInvDesc *descs, int nd, int maxm, const Ba
   if (nd <= 0) return hipSuccess;
   if (maxm <= 256) return level_launch<1, 256>(descs, nd, maxm, bs, g, info, retire, st);
   if (maxm <= 512) return level_launch<1, 512>(descs, nd, maxm, bs, g, info, retire, st);
-  if (maxm <= 1024) return level_launch<2, 512>(descs, nd, maxm, bs, g, info, retire, st);
+  if (maxm <= 1024) return level_launch<1, 1024>(descs, nd, maxm, bs, g, info, retire, st);
   return hipErrorInvalidValue;
 }
 
