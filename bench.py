@@ -50,12 +50,13 @@ KERNEL_SOURCES = {"gemm": ["kernels_gemm.hip", "kernel_util.hpp"],
                   "gj_panel": ["kernels_gj_blocked.hip", "gj_core.hpp", "kernel_util.hpp"],
                   "apply": ["kernels_mfma.hip", "kernels_apply.hip", "kernel_util.hpp"]}
 MEASURED_TRAFFIC = {
-    # gjb_leaf_kernel: FETCH_SIZE 171,449 KiB x 2.000 + WRITE_SIZE 2,363,296 KiB
+    # gjb_leaf_kernel: FETCH_SIZE 176,828 KiB x 2.000 + WRITE_SIZE 2,388,425 KiB
     # x 1.000 per launch (64 x 64 leaves, p = 16)
-    "gj_leaf[0]": ("5a0a3d7f43121ceb", 2771.1e6),
-    # gj_step_kernel (all 155 panel launches of a 64 x 64-leaf factorization):
-    # FETCH_SIZE 3,753 KiB x 2.000 + WRITE_SIZE 5,745 KiB x 1.000 per launch
-    "gj_panel[0]": ("0fdec31030b2ee30", 13.57e6),
+    "gj_leaf[0]": ("ed43f74ce702201b", 2807.9e6),
+    # gj_level_kernel + gj_level_rest_kernel (the five level launches of a
+    # 64 x 64-leaf factorization): FETCH_SIZE 26,371 KiB x 2.000 + WRITE_SIZE
+    # 11,559 KiB x 1.000 per level
+    "gj_panel[0]": ("e597f98f58b33be5", 65.84e6),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector = FP64 matrix
