@@ -61,7 +61,8 @@ struct DevArray {
 };
 
 enum StepKind {
-  S_GEMM, S_GJ_LEAF, S_GJ_MERGE, S_ZDIFF, S_PANEL, S_COLPERM, S_APPLY, S_COPY_F, S_VECOP
+  S_GEMM, S_GJ_LEAF, S_GJ_MERGE, S_ZDIFF, S_PANEL, S_COLPERM, S_APPLY, S_COPY_F, S_VECOP,
+  S_LEAF_B
 };
 
 constexpr int kPanelLevel = -(1 << 30);

@@ -201,12 +201,13 @@ namespace {
 struct Layout {
   // per box offsets (ws unless noted)
   std::vector<int64_t> T, X, S, LD, H, Pup, Pdn, Pups;   // -1 if absent
-  std::vector<int64_t> Tn_scr, Tmp_scr, Aie_scr, B_scr, W_scr, ipiv;
+  std::vector<int64_t> Tn_scr, Tmp_scr, B_scr, W_scr, ipiv;
   std::vector<int64_t> h, w, hn;                          // vec offsets
   std::vector<int64_t> Ub, Ubn, wb, hb, hbn;              // adjoint vec offsets
   std::vector<int64_t> map_fin, map_nat, map_gi, map_pi, map_slave;  // imap offsets
   std::vector<int64_t> Z0, map_psi;   // Neumann closure: zero sibling T (ws), data positions
   std::vector<int64_t> L_role;                 // ws, per role (5)
+  std::vector<int64_t> Mb_role;                // ws, per role: K_t L, t = 1..5 (build only)
   std::vector<int64_t> Dci, T0;                // ws, per (class*5 + role)
   int64_t ws = 0, scr = 0, vec = 0, imap = 0, ipiv_n = 0, solve_ws = 0;
 };
@@ -252,6 +253,36 @@ LeafRef leaf_reference(int p, int q) {
     else put(r, 1, iy, 1.0);
   }
   return R;
+}
+
+// The five fixed products M_t = K_t L (each mi x g4, column-major, ld mi;
+// stacked t = 1..5) with which leaf_b_kernel forms B = A_ci,ce L: restricted
+// to an interior row a = (iy, ix) and an exterior node b = (jy, jx), the
+// collocated operator is cxy(a) Dh(iy,jy) Dh(ix,jx) + [iy = jy] (cxx(a)
+// Dh2(ix,jx) + cx(a) Dh(ix,jx)) + [ix = jx] (cyy(a) Dh2(iy,jy) + cy(a)
+// Dh(iy,jy)) (Sec. 3.3), so K_1..K_5 are those five coefficient-free terms.
+std::vector<double> leaf_b_factors(const LeafRef &R, int p, const std::vector<double> &L,
+                                   int g4) {
+  const int mi = (int)R.ici.size(), me = (int)R.ice.size();
+  std::vector<double> M(size_t(5) * mi * g4, 0.0), K(size_t(5) * me);
+  for (int a = 0; a < mi; ++a) {
+    const int ga = R.ici[a], iy = ga / p, ix = ga % p;
+    for (int e = 0; e < me; ++e) {
+      const int gb = R.ice[e], jy = gb / p, jx = gb % p;
+      K[0 * me + e] = R.Dh[iy * p + jy] * R.Dh[ix * p + jx];
+      K[1 * me + e] = iy == jy ? R.Dh2[ix * p + jx] : 0.0;
+      K[2 * me + e] = iy == jy ? R.Dh[ix * p + jx] : 0.0;
+      K[3 * me + e] = ix == jx ? R.Dh2[iy * p + jy] : 0.0;
+      K[4 * me + e] = ix == jx ? R.Dh[iy * p + jy] : 0.0;
+    }
+    for (int t = 0; t < 5; ++t)
+      for (int j = 0; j < g4; ++j) {
+        double v = 0.0;
+        for (int e = 0; e < me; ++e) v += K[size_t(t) * me + e] * L[e + size_t(j) * me];
+        M[size_t(t) * mi * g4 + a + size_t(j) * mi] = v;
+      }
+  }
+  return M;
 }
 
 // side order of a leaf with role r: the three kept sides, then the shared one
@@ -388,7 +419,7 @@ static int plan_layout(PlanCtx &C) {
   auto &ws_blocks = C.ws_blocks;
   Lo.T.assign(nb, -1); Lo.X.assign(nb, -1); Lo.S.assign(nb, -1); Lo.LD.assign(nb, -1);
   Lo.H.assign(nb, -1); Lo.Pup.assign(nb, -1); Lo.Pdn.assign(nb, -1); Lo.Pups.assign(nb, -1);
-  Lo.Tn_scr.assign(nb, -1); Lo.Tmp_scr.assign(nb, -1); Lo.Aie_scr.assign(nb, -1);
+  Lo.Tn_scr.assign(nb, -1); Lo.Tmp_scr.assign(nb, -1);
   Lo.B_scr.assign(nb, -1); Lo.W_scr.assign(nb, -1); Lo.ipiv.assign(nb, -1);
   Lo.h.assign(nb, -1); Lo.w.assign(nb, -1); Lo.hn.assign(nb, -1);
   Lo.Ub.assign(nb, -1); Lo.Ubn.assign(nb, -1); Lo.wb.assign(nb, -1); Lo.hb.assign(nb, -1);
@@ -469,10 +500,12 @@ static int plan_layout(PlanCtx &C) {
   // reference matrices per role / size class
   LeafRef R = leaf_reference(p, q);
   Lo.L_role.assign(5, -1);
+  std::vector<std::vector<double>> role_L(5);
   for (int r = 0; r < 5; ++r) {
     int so[4];
     role_sides(r, so);
-    std::vector<double> L(size_t(me) * g4);
+    std::vector<double> &L = role_L[r];
+    L.assign(size_t(me) * g4, 0.0);
     for (int j = 0; j < 4; ++j)
       std::memcpy(&L[size_t(me) * j * q], &R.Lnat[size_t(me) * so[j] * q],
                   sizeof(double) * me * q);
@@ -480,6 +513,12 @@ static int plan_layout(PlanCtx &C) {
     ws_blocks.push_back({Lo.L_role[r], L});
   }
   Lo.solve_ws = Lo.ws;
+  // the five fixed products K_t L of each role for B = A_ci,ce L (build only)
+  Lo.Mb_role.assign(5, -1);
+  for (int r = 0; r < 5; ++r) {
+    Lo.Mb_role[r] = ws_take(5 * int64_t(mi) * g4);
+    ws_blocks.push_back({Lo.Mb_role[r], leaf_b_factors(R, p, role_L[r], g4)});
+  }
   // Neumann closure boxes merge with a sibling whose T is zero
   Lo.Z0.assign(nb, -1);
   for (int b = 0; b < nb; ++b)
@@ -534,7 +573,6 @@ static int plan_layout(PlanCtx &C) {
     const int li = pl.leaves[i];
     if (!own(li)) continue;
     if (Lo.T[li] < 0) Lo.T[li] = ws_take(int64_t(g4) * g4);   // single-leaf root
-    Lo.Aie_scr[li] = scr_take(int64_t(mi) * me);
     Lo.B_scr[li] = scr_take(int64_t(mi) * g4);
   }
   for (int li : pl.leaves)
@@ -655,7 +693,6 @@ static int plan_build_program(PlanCtx &C) {
     const Ref fr = f_ref(i);
     d.F = fr.off;
     d.fbuf = fr.buf;
-    d.Aie = Lo.Aie_scr[li];
     d.sx = 2.0 / sc.first;
     d.sy = 2.0 / sc.second;
     d.info = i;
@@ -663,6 +700,8 @@ static int plan_build_program(PlanCtx &C) {
     d.hrows = leaf_kernel_forms_h(p, g4) ? g4 : 0;
     d.Dci = Lo.Dci[size_t(pl.leaf_class[i]) * 5 + pl.boxes[li].role];
     d.H = Lo.H[li];
+    d.Bout = Lo.B_scr[li];
+    d.Mb = Lo.Mb_role[pl.boxes[li].role];
     leafd.push_back(d);
   }
   // the leaves whose operators the build computes (all but deduplicated
@@ -682,6 +721,28 @@ static int plan_build_program(PlanCtx &C) {
     s.d0 = bl0 + c0;
     s.nd = c1 - c0;
     prog.push_back(s);
+    {
+      // B = A_ci,ce L: the step's leaves grouped by role in chunks of up to
+      // kLeafBChunk; imap holds the leaf descriptor indices (lidx) and the
+      // chunks' [first, count] pairs
+      std::vector<int32_t> lidx, chunks;
+      for (int r = 0; r < 5; ++r) {
+        int n = 0;
+        for (int ci = c0; ci < c1; ++ci) {
+          if (pl.boxes[pl.leaves[bl[ci]]].role != r) continue;
+          if (n % kLeafBChunk == 0) { chunks.push_back((int32_t)lidx.size()); chunks.push_back(0); }
+          lidx.push_back(int32_t(bl0 + ci));
+          ++chunks.back();
+          ++n;
+        }
+      }
+      Step sb{S_LEAF_B};
+      sb.d0 = C.imap_put(lidx);
+      sb.tmap0 = C.imap_put(chunks);
+      sb.nd = c1 - c0;
+      sb.ntiles = (int64_t)chunks.size() / 2;
+      prog.push_back(sb);
+    }
     GemmList a, b2, c;
     for (int ci = c0; ci < c1; ++ci) {
       const int i = bl[ci];
@@ -690,13 +751,6 @@ static int plan_build_program(PlanCtx &C) {
       const Ref F = f_ref(i);
       const int64_t Dci = Lo.Dci[size_t(cls) * 5 + role], T0 = Lo.T0[size_t(cls) * 5 + role];
       GemmDesc g{};
-      // B = A_ci,ce L
-      g = GemmDesc{};
-      g.M = mi; g.N = g4; g.K = me;
-      g.A = ref(BUF_SCR, Lo.Aie_scr[li], mi); g.B = ref(BUF_WS, Lo.L_role[role], me);
-      g.C = ref(BUF_SCR, Lo.B_scr[li], mi); g.D = noref();
-      g.crow = g.ccol = -1; g.alpha = 1.0; g.beta = 0.0;
-      a.add(g);
       // H = D_ge,ci F (unless the leaf kernel formed it)
       if (!leaf_kernel_forms_h(p, g4)) {
         g = GemmDesc{};
@@ -1044,7 +1098,6 @@ static int plan_solve_programs(PlanCtx &C) {
       // then u_ci += F g
       for (int i = 0; i < nleaf; ++i) {
         LeafDesc d = leafd[i];
-        d.Aie = -1;
         d.hrows = 0;                  // H is stored already
         leafd.push_back(d);
       }
@@ -1407,6 +1460,7 @@ static void annotate_work(std::vector<Step> &prog, const GemmList &gl,
       switch (s.kind) {
         case S_GEMM: w += 2.0 * gl.d[i].M * double(gl.d[i].N) * gl.d[i].K; break;
         case S_GJ_LEAF: w += leaf_w; break;
+        case S_LEAF_B: w += 10.0 * double(mi) * g4; break;
         case S_GJ_MERGE: w += 2.0 * double(mv[i].m) * mv[i].m * mv[i].m; break;
         case S_PANEL: {
           // update by panel kb of the other columns, sweep of panel kb + NB
@@ -1591,7 +1645,11 @@ int run_prog(hps_handle *H, std::vector<Step> &prog, Bases bs, int nrhs, int pre
         break;
       case S_GJ_LEAF:
         e = launch_gj_leaf(H->p, H->d_leaf.p + s.d0, (int)s.nd, bs, H->aux.p + H->Dh_off,
-                           H->aux.p + H->Dh2_off, H->imap.p + H->ice_map, H->me, H->info.p, st);
+                           H->aux.p + H->Dh2_off, H->info.p, st);
+        break;
+      case S_LEAF_B:
+        e = launch_leaf_b(H->d_leaf.p, H->imap.p + s.tmap0, (int)s.ntiles, H->imap.p + s.d0, bs,
+                          H->p, H->g4, st);
         break;
       case S_GJ_MERGE:
         e = launch_gj_merge(s.cls, H->d_minv.p + s.d0, (int)s.nd, bs, H->info.p, st);

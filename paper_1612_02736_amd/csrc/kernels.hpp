@@ -15,6 +15,8 @@ int panel_nb(int maxm);           // panel width used for a level of size maxm
 // tmap[t] = index (into descs) of the descriptor that owns tile t
 // leaves per chunk of the storage-economic build and solve
 constexpr int kEconChunk = 1024;
+// leaves of one role per workgroup of leaf_b_kernel
+constexpr int kLeafBChunk = 16;
 // info code of a leaf Gauss-Jordan whose flag-synchronised sweep gave up
 // waiting (never in a correct run)
 constexpr int kGjSyncTimeout = -0x7fffffff;
@@ -28,11 +30,14 @@ int gj_leaf_supported(int p);
 // padding rows)
 inline bool leaf_kernel_forms_h(int p, int g4) { return p == 16 && 196 + g4 <= 256; }
 hipError_t launch_gjb_leaf(const LeafDesc *descs, int nleaf, const Bases &bs, const double *Dh,
-                           const double *Dh2, const int32_t *ice, int me, int32_t *info,
-                           hipStream_t st);
+                           const double *Dh2, int32_t *info, hipStream_t st);
 hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
-                          const double *Dh, const double *Dh2, const int32_t *ice,
-                          int me, int32_t *info, hipStream_t st);
+                          const double *Dh, const double *Dh2, int32_t *info, hipStream_t st);
+// B = A_ci,ce L of every leaf (mi x g4), from the role's products K_t L;
+// leaves in chunks of one role (chunks: [first, count] pairs into lidx, the
+// leaf descriptor indices)
+hipError_t launch_leaf_b(const LeafDesc *descs, const int32_t *chunks, int nchunks,
+                         const int32_t *lidx, const Bases &bs, int p, int g4, hipStream_t st);
 int gj_merge_class(int m);
 hipError_t launch_gj_merge(int cls, const MergeInvDesc *descs, int nd, const Bases &bs,
                            int32_t *info, hipStream_t st);

@@ -10,7 +10,7 @@ template <int P, int TR, int TC, int RA, int CB>
 __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
     const LeafDesc *__restrict__ descs, int nleaf, Bases bs,
     const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
-    const int32_t *__restrict__ ice, int me, int32_t *__restrict__ info) {
+    int32_t *__restrict__ info) {
   constexpr int PI = P - 2, MI = PI * PI;
   __shared__ GJShared<TR, TC, RA, CB> sh;
   __shared__ double cf[6][P * P];
@@ -34,14 +34,6 @@ __global__ __launch_bounds__((gj_threads<TR, TC>())) void gj_leaf_kernel(
     return v;
   };
   auto grid_of = [](int a) { const int y = a / PI; return (y + 1) * P + (a - y * PI) + 1; };
-  // A_ci,ce (mi x me, column-major) for the leaf products
-  if (d.Aie >= 0) {
-    double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
-    for (int idx = tid; idx < MI * me; idx += blockDim.x) {
-      const int a = idx % MI, e = idx / MI;
-      Aie[idx] = entry(grid_of(a), ice[e]);
-    }
-  }
   int tr, tc;
   gj_owner<TR, TC, RA, CB>(tid, tr, tc);
   double a[RA][CB];
@@ -65,7 +57,7 @@ template <int P, int NW, int RA, int CB>
 __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
     const LeafDesc *__restrict__ descs, int nleaf, Bases bs,
     const double *__restrict__ Dh_g, const double *__restrict__ Dh2_g,
-    const int32_t *__restrict__ ice, int me, int32_t *__restrict__ info) {
+    int32_t *__restrict__ info) {
   constexpr int PI = P - 2, MI = PI * PI;
   static_assert(64 * RA >= MI && NW * CB >= MI, "block too small");
   __shared__ GJ2Shared<NW, RA> sh;
@@ -89,13 +81,6 @@ __global__ __launch_bounds__(NW * 64) void gj2_leaf_kernel(
     return v;
   };
   auto grid_of = [](int a) { const int y = a / PI; return (y + 1) * P + (a - y * PI) + 1; };
-  if (d.Aie >= 0) {             // A_ci,ce for the leaf products
-    double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
-    for (int idx = tid; idx < MI * me; idx += NW * 64) {
-      const int a = idx % MI, e = idx / MI;
-      Aie[idx] = entry(grid_of(a), ice[e]);
-    }
-  }
   // rows MI .. MI + hrows - 1 (padding rows otherwise) carry D_ge,ci: they
   // are never pivots, and the sweeps turn them into -D_ge,ci A_ci,ci^-1 = -H
   // (with the columns in pivot order), the flux map of the particular
@@ -160,32 +145,32 @@ static bool leaf_rank1_p16() {
   return r1;
 }
 
+
 hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &bs,
-                          const double *Dh, const double *Dh2, const int32_t *ice,
-                          int me, int32_t *info, hipStream_t st) {
+                          const double *Dh, const double *Dh2, int32_t *info, hipStream_t st) {
   if (nleaf <= 0) return hipSuccess;
   switch (p) {
     case 16:
       if (!leaf_rank1_p16())
-        return launch_gjb_leaf(descs, nleaf, bs, Dh, Dh2, ice, me, info, st);
+        return launch_gjb_leaf(descs, nleaf, bs, Dh, Dh2, info, st);
       hipLaunchKernelGGL((gj2_leaf_kernel<16, 8, 4, 25>), dim3(nleaf), dim3(512), 0, st, descs,
-                         nleaf, bs, Dh, Dh2, ice, me, info);
+                         nleaf, bs, Dh, Dh2, info);
       break;
     case 12:
       hipLaunchKernelGGL((gj_leaf_kernel<12, 20, 20, 5, 5>), dim3(nleaf), dim3(gj_threads<20, 20>()), 0, st,
-                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+                         descs, nleaf, bs, Dh, Dh2, info);
       break;
     case 10:
       hipLaunchKernelGGL((gj_leaf_kernel<10, 8, 8, 8, 8>), dim3(nleaf), dim3(64), 0, st,
-                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+                         descs, nleaf, bs, Dh, Dh2, info);
       break;
     case 8:
       hipLaunchKernelGGL((gj_leaf_kernel<8, 8, 8, 5, 5>), dim3(nleaf), dim3(64), 0, st,
-                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+                         descs, nleaf, bs, Dh, Dh2, info);
       break;
     case 6:
       hipLaunchKernelGGL((gj_leaf_kernel<6, 8, 8, 2, 2>), dim3(nleaf), dim3(64), 0, st,
-                         descs, nleaf, bs, Dh, Dh2, ice, me, info);
+                         descs, nleaf, bs, Dh, Dh2, info);
       break;
     default:
       return hipErrorInvalidValue;
@@ -195,5 +180,67 @@ hipError_t launch_gj_leaf(int p, const LeafDesc *descs, int nleaf, const Bases &
 
 int gj_leaf_supported(int p) { return p == 16 || p == 12 || p == 10 || p == 8 || p == 6; }
 
+// B = A_ci,ce L for every leaf (Sec. 3.3: the leaf's particular-solution
+// flux map needs S_ci = -F A_ci,ce L).  An interior row a of the collocated
+// operator restricted to the exterior nodes is
+//   cxy(a) K1(a, :) + cxx(a) K2(a, :) + cx(a) K3(a, :) + cyy(a) K4(a, :) + cy(a) K5(a, :)
+// with fixed K_t (products of the reference differentiation matrices), so
+// B(a, :) = sum_t c_t(a) M_t(a, :) with M_t = K_t L formed once per role on
+// the host: five row-scaled fixed matrices instead of a product with the
+// leaf's A_ci,ce.  Workgroup (c, jb) takes chunk c of leaves that share a
+// role (chunks[2c] = first entry in lidx, chunks[2c + 1] = count) and the
+// columns 12 jb .. 12 jb + 11 of B: thread a keeps row a of that slice of the
+// five M_t in registers across the chunk's leaves and writes row a of each
+// leaf's B slice (column-major, ld mi).
+constexpr int kLeafBCols = 12;
+
+__global__ __launch_bounds__(256) void leaf_b_kernel(const LeafDesc *__restrict__ descs,
+                                                     Bases bs, const int32_t *__restrict__ chunks,
+                                                     const int32_t *__restrict__ lidx, int p,
+                                                     int g4) {
+  const int first = chunks[2 * blockIdx.x], cnt = chunks[2 * blockIdx.x + 1];
+  const int pi = p - 2, mi = pi * pi, pp = p * p;
+  const int a = threadIdx.x;
+  if (a >= mi) return;
+  const int j0 = kLeafBCols * blockIdx.y, nj = min(kLeafBCols, g4 - j0);
+  const int64_t tot = int64_t(mi) * g4;
+  const int y = a / pi, ga = (y + 1) * p + (a - y * pi) + 1;   // grid node of interior row a
+  double m[5][kLeafBCols];
+  {
+    const double *M = (const double *)bs.d[BUF_WS] + descs[lidx[first]].Mb;
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+      for (int j = 0; j < kLeafBCols; ++j)
+        m[t][j] = j < nj ? M[t * tot + a + int64_t(j0 + j) * mi] : 0.0;
+  }
+#pragma unroll 4
+  for (int k = 0; k < cnt; ++k) {
+    const LeafDesc &d = descs[lidx[first + k]];
+    const double *cf = (const double *)bs.d[BUF_COEF] + d.coef;
+    const double sx = d.sx, sy = d.sy;
+    const double c1 = -2.0 * cf[pp + ga] * sx * sy, c2 = -cf[ga] * sx * sx,
+                 c3 = cf[3 * pp + ga] * sx, c4 = -cf[2 * pp + ga] * sy * sy,
+                 c5 = cf[4 * pp + ga] * sy;
+    double *B = (double *)bs.d[BUF_SCR] + d.Bout + a + int64_t(j0) * mi;
+#pragma unroll
+    for (int j = 0; j < kLeafBCols; ++j) {
+      double v = c1 * m[0][j];
+      v = fma(c2, m[1][j], v);
+      v = fma(c3, m[2][j], v);
+      v = fma(c4, m[3][j], v);
+      v = fma(c5, m[4][j], v);
+      if (j < nj) B[int64_t(j) * mi] = v;
+    }
+  }
+}
+
+hipError_t launch_leaf_b(const LeafDesc *descs, const int32_t *chunks, int nchunks,
+                         const int32_t *lidx, const Bases &bs, int p, int g4, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(leaf_b_kernel, dim3(nchunks, (g4 + kLeafBCols - 1) / kLeafBCols), dim3(256),
+                     0, st, descs, bs, chunks, lidx, p, g4);
+  return hipGetLastError();
+}
 
 }  // namespace hps

@@ -439,8 +439,7 @@ __device__ __forceinline__ void sweep_tail(int lane, Shared &sh) {
 
 __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
     const LeafDesc *__restrict__ descs, int nleaf, Bases bs, const double *__restrict__ Dh_g,
-    const double *__restrict__ Dh2_g, const int32_t *__restrict__ ice, int me,
-    int32_t *__restrict__ info) {
+    const double *__restrict__ Dh2_g, int32_t *__restrict__ info) {
   using namespace gjb;
   __shared__ Shared sh;
   const int leaf = blockIdx.x;
@@ -464,8 +463,7 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
     sh.tail_done = -1;
     sh.abort = 0;
   }
-  // -2: still computing A_ci,ce from the tables in slot 1 (wavefronts 1..)
-  if (tid < NS) sh.done[tid] = tid == 0 ? -1 : -2;
+  if (tid < NS) sh.done[tid] = -1;
   __syncthreads();
   const double sx = d.sx, sy = d.sy;
   auto entry = [&](int ga, int gb) -> double {
@@ -545,14 +543,7 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
   double *wt = sh.wt[w];
   if (w == 0) {
     sweep_strip(acc, 0, lane, sh);
-  } else if (d.Aie >= 0) {      // A_ci,ce for the leaf products, meanwhile
-    double *Aie = (double *)bs.d[BUF_SCR] + d.Aie;
-    for (int idx = tid - 64; idx < MI * me; idx += NT - 64) {
-      const int a = idx % MI, e = idx / MI;
-      Aie[idx] = entry(grid_of(a), ice[e]);
-    }
   }
-  if (w != 0) post(sh.done[w], -1, lane);
   for (int q = 0; q < NS; ++q) {
     if (w == q) {
       // this wavefront's strip is panel q ([P0, P1]); the tail takes the
@@ -589,8 +580,8 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
       update_strip16(acc, q, lane, wt, sh);
       post(sh.done[w], q, lane);
       if (owner) {
+        // the tables in slot 1 are read only before the barrier above
         if (q + 1 >= NSLOT) wait_all_done(sh, q + 1 - NSLOT);
-        else if (q + 1 == 1) wait_all_done(sh, -1);   // tables in slot 1 no longer read
         sweep_strip(acc, q + 1, lane, sh);
         __builtin_amdgcn_s_setprio(0);
       }
@@ -627,11 +618,10 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
 }
 
 hipError_t launch_gjb_leaf(const LeafDesc *descs, int nleaf, const Bases &bs, const double *Dh,
-                           const double *Dh2, const int32_t *ice, int me, int32_t *info,
-                           hipStream_t st) {
+                           const double *Dh2, int32_t *info, hipStream_t st) {
   if (nleaf <= 0) return hipSuccess;
   hipLaunchKernelGGL(gjb_leaf_kernel, dim3(nleaf), dim3(gjb::NT), 0, st, descs, nleaf, bs, Dh,
-                     Dh2, ice, me, info);
+                     Dh2, info);
   return hipGetLastError();
 }
 

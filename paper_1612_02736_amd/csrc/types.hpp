@@ -48,7 +48,6 @@ struct GemmDesc {
 struct LeafDesc {
   int64_t coef;   // BUF_COEF offset of the leaf's [6][p*p] coefficients
   int64_t F;      // offset of F (mi x mi, ld mi) in buffer fbuf
-  int64_t Aie;    // BUF_SCR offset of A_ci,ce (mi x me, ld mi); < 0: not written
   double sx, sy;  // 2/hx, 2/hy
   int32_t info;   // slot in the info array
   int32_t fbuf;   // buffer of F: BUF_WS (stored) or BUF_SCR (recomputed per chunk)
@@ -57,6 +56,10 @@ struct LeafDesc {
   // hrows = 0: H is not formed here
   int64_t Dci, H;
   int32_t hrows, pad;
+  // leaf_b_kernel: B = A_ci,ce L (mi x 4q, ld mi) at BUF_SCR offset Bout, from
+  // the five products K_t L of the leaf's role (BUF_WS offset Mb, each
+  // mi x 4q, ld mi)
+  int64_t Bout, Mb;
 };
 
 // Interface block of a merge: X = (T33a - T33b)^-1.

@@ -409,7 +409,7 @@ def debug_box_op(solver, box, which, shape):
 
 
 PROFILE_KINDS = {0: "gemm", 1: "gj_leaf", 2: "gj_interface", 3: "interface_diff",
-                 4: "gj_panel", 5: "gj_colperm", 6: "apply"}
+                 4: "gj_panel", 5: "gj_colperm", 6: "apply", 9: "leaf_b"}
 
 
 def debug_profile(solver, enable=True):
