@@ -842,26 +842,24 @@ static int plan_build_program(PlanCtx &C) {
       if (B.coarsened) Cout = ref(BUF_SCR, Lo.Tn_scr[b], en);
       else { Cout = ref(BUF_WS, Lo.T[b], ef); pr = Lo.map_pi[b]; }
       const int64_t Ta = Lo.T[B.alpha], Tb = Lo.T[B.beta];
-      for (int bi = 0; bi < 2; ++bi)
-        for (int bj = 0; bj < 2; ++bj) {
-          GemmDesc t{};
-          t.M = bi == 0 ? n1 : n2;
-          t.N = bj == 0 ? n1 : n2;
-          t.K = m;
-          t.A = bi == 0 ? ref(BUF_WS, Ta + int64_t(n1) * ea, ea) : ref(BUF_WS, Tb + int64_t(n2) * eb, eb);
-          t.B = ref(BUF_WS, Lo.S[b] + (bj == 0 ? 0 : int64_t(n1) * m), m);
-          if (bi == bj) t.D = bi == 0 ? ref(BUF_WS, Ta, ea) : ref(BUF_WS, Tb, eb);
-          else t.D = noref();
-          t.alpha = 1.0; t.beta = (bi == bj) ? 1.0 : 0.0;
-          const int r0 = bi == 0 ? 0 : n1, c0 = bj == 0 ? 0 : n1;
-          if (pr >= 0) {
-            t.C = Cout; t.crow = pr + r0; t.ccol = pr + c0;
-          } else {
-            t.C = ref(Cout.buf, Cout.off + r0 + int64_t(c0) * en, en);
-            t.crow = t.ccol = -1;
-          }
-          tg.add(t);
-        }
+      // one product: rows 0..n1-1 of [T13a; T23b] from T_alpha, the rest
+      // from T_beta, and the block-diagonal part from both
+      GemmDesc t{};
+      t.M = en; t.N = en; t.K = m;
+      const Ref a1 = ref(BUF_WS, Ta + int64_t(n1) * ea, ea), a2 = ref(BUF_WS, Tb + int64_t(n2) * eb, eb);
+      const Ref d1 = ref(BUF_WS, Ta, ea), d2 = ref(BUF_WS, Tb, eb);
+      if (n1 == 0) { t.A = a2; t.D = d2; }
+      else if (n2 == 0) { t.A = a1; t.D = d1; }
+      else { t.A = a1; t.D = d1; t.A2 = a2; t.D2 = d2; t.msplit = n1; }
+      t.B = ref(BUF_WS, Lo.S[b], m);
+      t.alpha = 1.0; t.beta = 1.0;
+      if (pr >= 0) {
+        t.C = Cout; t.crow = pr; t.ccol = pr;
+      } else {
+        t.C = ref(Cout.buf, Cout.off, en);
+        t.crow = t.ccol = -1;
+      }
+      tg.add(t);
       if (B.coarsened) {
         GemmDesc u{};
         u.M = en; u.N = ef; u.K = en;

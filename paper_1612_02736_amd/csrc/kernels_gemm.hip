@@ -41,7 +41,12 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
   const int ar = tid % TM, ak = tid / TM;         // A: row ar, k = ak + AKS s
   const int bk = tid % BK, bc = tid / BK;         // B: k = bk, cols bc + BCS s
   const bool arow_ok = row0 + ar < M;
-  const double *Ap = A + (row0 + ar);
+  const int msplit = d.msplit;
+  // rows from msplit on come from the second A source, if any
+  const bool a2 = msplit > 0 && row0 + ar >= msplit;
+  const double *Ap = a2 ? (const double *)bs.d[d.A2.buf] + d.A2.off + (row0 + ar - msplit)
+                        : A + (row0 + ar);
+  const int lda_r = a2 ? d.A2.ld : lda;
   dbl4 acc[NI][NJ];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
@@ -52,7 +57,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
 #pragma unroll
     for (int s = 0; s < NA; ++s) {
       const int gk = k0 + ak + AKS * s;
-      ra[s] = (arow_ok && gk < K) ? Ap[int64_t(gk) * lda] : 0.0;
+      ra[s] = (arow_ok && gk < K) ? Ap[int64_t(gk) * lda_r] : 0.0;
     }
     const int gk = k0 + bk;
 #pragma unroll
@@ -122,6 +127,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
   }
   double *C = (double *)bs.d[d.C.buf] + d.C.off;
   const double *D = d.D.buf >= 0 ? (const double *)bs.d[d.D.buf] + d.D.off : nullptr;
+  const double *D2 = msplit > 0 && d.D2.buf >= 0 ? (const double *)bs.d[d.D2.buf] + d.D2.off
+                                                 : nullptr;
   const int32_t *crow = d.crow >= 0 ? bs.imap + d.crow : nullptr;
   const int32_t *ccol = d.ccol >= 0 ? bs.imap + d.ccol : nullptr;
 #pragma unroll
@@ -136,7 +143,13 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
         const int col = wc0 + j * 16 + (lane & 15);
         if (row < M && col < N) {
           double val = d.alpha * acc[i][j][v];
-          if (D) val += d.beta * D[row + int64_t(col) * d.D.ld];
+          if (msplit == 0) {
+            if (D) val += d.beta * D[row + int64_t(col) * d.D.ld];
+          } else if (row < msplit && col < msplit) {
+            if (D) val += d.beta * D[row + int64_t(col) * d.D.ld];
+          } else if (row >= msplit && col >= msplit) {
+            if (D2) val += d.beta * D2[(row - msplit) + int64_t(col - msplit) * d.D2.ld];
+          }
           const int64_t cr = crow ? crow[row] : row;
           const int64_t cc = ccol ? ccol[col] : col;
           C[cr + cc * d.C.ld] = val;

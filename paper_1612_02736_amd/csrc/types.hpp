@@ -34,13 +34,19 @@ struct Ref {
 };
 
 // C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * D(i,j), written at
-// C[crow(i) + ccol(j) * ldc] (maps optional).
+// C[crow(i) + ccol(j) * ldc] (maps optional).  With msplit > 0 the rows of A
+// from msplit on come from A2 (its row i - msplit), and D is block-diagonal:
+// D(i,j) for i, j < msplit, D2(i - msplit, j - msplit) for i, j >= msplit,
+// 0 elsewhere (the merge's T = blkdiag(T11a, T22b) + [T13a; T23b] S as one
+// product).
 struct GemmDesc {
   int32_t M, N, K, tn;
   int64_t tile0;
   Ref A, B, C, D;
   int64_t crow, ccol;   // offsets into imap, -1 = identity
   double alpha, beta;
+  Ref A2, D2;
+  int32_t msplit, pad;
 };
 
 // Leaf interior block: assemble A_ci,ci and A_ci,ce from the nodal
