@@ -47,6 +47,49 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
   const double *Ap = a2 ? (const double *)bs.d[d.A2.buf] + d.A2.off + (row0 + ar - msplit)
                         : A + (row0 + ar);
   const int lda_r = a2 ? d.A2.ld : lda;
+  double *C = (double *)bs.d[d.C.buf] + d.C.off;
+  const double *D = d.D.buf >= 0 ? (const double *)bs.d[d.D.buf] + d.D.off : nullptr;
+  const double *D2 = msplit > 0 && d.D2.buf >= 0 ? (const double *)bs.d[d.D2.buf] + d.D2.off
+                                                 : nullptr;
+  const int32_t *crow = d.crow >= 0 ? bs.imap + d.crow : nullptr;
+  const int32_t *ccol = d.ccol >= 0 ? bs.imap + d.ccol : nullptr;
+  // f64 16x16x4 result layout: lane l, register v holds row (l >> 4) + 4 v,
+  // column l & 15
+  auto out_row = [&](int i, int v) { return wr0 + i * 16 + (lane >> 4) + 4 * v; };
+  auto out_col = [&](int j) { return wc0 + j * 16 + (lane & 15); };
+  // beta D(row, col), block-diagonal with msplit > 0
+  auto dval = [&](int row, int col) -> double {
+    if (msplit == 0) return D ? d.beta * D[row + int64_t(col) * d.D.ld] : 0.0;
+    if (row < msplit && col < msplit) return D ? d.beta * D[row + int64_t(col) * d.D.ld] : 0.0;
+    if (row >= msplit && col >= msplit && D2)
+      return d.beta * D2[(row - msplit) + int64_t(col - msplit) * d.D2.ld];
+    return 0.0;
+  };
+  // Small tiles (one or two MFMA tiles per wavefront, mostly short-K merge
+  // products): the epilogue's D values and output maps are loaded now, so
+  // their latency overlaps the operand fetch instead of following the MFMAs.
+  constexpr bool PRE = NI * NJ <= 2;
+  double dpre[PRE ? NI : 1][PRE ? NJ : 1][4];
+  int64_t crp[PRE ? NI : 1][4], ccp[PRE ? NJ : 1];
+  if constexpr (PRE) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = out_row(i, v);
+        crp[i][v] = row < M ? (crow ? crow[row] : row) : 0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int col = out_col(j);
+          dpre[i][j][v] = (row < M && col < N) ? dval(row, col) : 0.0;
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = out_col(j);
+      ccp[j] = col < N ? (ccol ? ccol[col] : col) : 0;
+    }
+  }
   dbl4 acc[NI][NJ];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
@@ -125,33 +168,25 @@ __global__ __launch_bounds__(256, OCC) void gemm_f64_kernel(
     __syncthreads();
     buf ^= 1;
   }
-  double *C = (double *)bs.d[d.C.buf] + d.C.off;
-  const double *D = d.D.buf >= 0 ? (const double *)bs.d[d.D.buf] + d.D.off : nullptr;
-  const double *D2 = msplit > 0 && d.D2.buf >= 0 ? (const double *)bs.d[d.D2.buf] + d.D2.off
-                                                 : nullptr;
-  const int32_t *crow = d.crow >= 0 ? bs.imap + d.crow : nullptr;
-  const int32_t *ccol = d.ccol >= 0 ? bs.imap + d.ccol : nullptr;
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        // f64 16x16x4 result layout: lane l, register v holds row (l >> 4) + 4 v,
-        // column l & 15
-        const int row = wr0 + i * 16 + (lane >> 4) + 4 * v;
-        const int col = wc0 + j * 16 + (lane & 15);
+        const int row = out_row(i, v), col = out_col(j);
         if (row < M && col < N) {
           double val = d.alpha * acc[i][j][v];
-          if (msplit == 0) {
-            if (D) val += d.beta * D[row + int64_t(col) * d.D.ld];
-          } else if (row < msplit && col < msplit) {
-            if (D) val += d.beta * D[row + int64_t(col) * d.D.ld];
-          } else if (row >= msplit && col >= msplit) {
-            if (D2) val += d.beta * D2[(row - msplit) + int64_t(col - msplit) * d.D2.ld];
+          int64_t cr, cc;
+          if constexpr (PRE) {
+            val += dpre[i][j][v];
+            cr = crp[i][v];
+            cc = ccp[j];
+          } else {
+            val += dval(row, col);
+            cr = crow ? crow[row] : row;
+            cc = ccol ? ccol[col] : col;
           }
-          const int64_t cr = crow ? crow[row] : row;
-          const int64_t cc = ccol ? ccol[col] : col;
           C[cr + cc * d.C.ld] = val;
         }
       }
