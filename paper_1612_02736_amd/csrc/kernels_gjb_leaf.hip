@@ -448,13 +448,18 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, n = lane & 15;
-  // coefficient and reference tables in slot 1 until the first sweep of it
-  double *cf = sh.slot[1], *Dh = cf + 6 * P * P, *Dh2 = Dh + P * P;
+  // coefficient and reference tables in slot 1 until the first sweep of it;
+  // the rows of Dh and Dh2 are padded to DS doubles so that the lanes of one
+  // assembly step, which read one column index jx in up to 16 different rows
+  // ix, hit different LDS banks
+  constexpr int DS = P + 1;
+  static_assert(6 * P * P + 2 * P * DS <= NR * S, "tables must fit in one slot");
+  double *cf = sh.slot[1], *Dh = cf + 6 * P * P, *Dh2 = Dh + P * DS;
   const double *coef = (const double *)bs.d[BUF_COEF] + d.coef;
   for (int i = tid; i < 6 * P * P; i += NT) cf[i] = coef[i];
   for (int i = tid; i < P * P; i += NT) {
-    Dh[i] = Dh_g[i];
-    Dh2[i] = Dh2_g[i];
+    Dh[i + i / P] = Dh_g[i];
+    Dh2[i + i / P] = Dh2_g[i];
   }
   for (int i = tid; i < NR; i += NT) sh.stepof[i] = -1;
   if (tid == 0) {
@@ -468,10 +473,10 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
   const double sx = d.sx, sy = d.sy;
   auto entry = [&](int ga, int gb) -> double {
     const int iy = ga / P, ix = ga - iy * P, jy = gb / P, jx = gb - jy * P;
-    double v = -2.0 * cf[P * P + ga] * sx * sy * Dh[iy * P + jy] * Dh[ix * P + jx];
-    if (iy == jy) v += -cf[ga] * sx * sx * Dh2[ix * P + jx] + cf[3 * P * P + ga] * sx * Dh[ix * P + jx];
+    double v = -2.0 * cf[P * P + ga] * sx * sy * Dh[iy * DS + jy] * Dh[ix * DS + jx];
+    if (iy == jy) v += -cf[ga] * sx * sx * Dh2[ix * DS + jx] + cf[3 * P * P + ga] * sx * Dh[ix * DS + jx];
     if (ix == jx)
-      v += -cf[2 * P * P + ga] * sy * sy * Dh2[iy * P + jy] + cf[4 * P * P + ga] * sy * Dh[iy * P + jy];
+      v += -cf[2 * P * P + ga] * sy * sy * Dh2[iy * DS + jy] + cf[4 * P * P + ga] * sy * Dh[iy * DS + jy];
     if (ga == gb) v += cf[5 * P * P + ga];
     return v;
   };
@@ -484,19 +489,23 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
     return 0.0;
   };
   const int col = 16 * w + n;
-  // The strip's entries, 32 rows at a time, through a 4 KB LDS stage of this
-  // wavefront (slot 0 and the W^T buffers are free until the first sweep).
+  // The strip's entries, 32 rows at a time, through an LDS stage of this
+  // wavefront (slots 0 and 2 are free until the first sweep); its rows are
+  // padded to SD doubles, since with 16 the 16 rows written by one pass of
+  // lanes would all start in the same LDS bank.
   // Lane pair (2 rr, 2 rr + 1) computes row 32 tc + rr, columns 8 (lane & 1)
   // .. + 7 of the strip, with the row's coefficients loaded once: entry
   // (a, b) of A_ci,ci is cxy(a) Dh(iy, jy) Dh(ix, jx) + [iy = jy] (cxx(a)
   // Dh2(ix, jx) + cx(a) Dh(ix, jx)) + [ix = jx] (cyy(a) Dh2(iy, jy) + cy(a)
   // Dh(iy, jy)) + [a = b] c(a) (grid indices of interior nodes a and b).
-  double *stage = w < 9 ? &sh.slot[0][0] + 512 * w : &sh.wt[0][0] + 512 * (w - 9);
+  constexpr int SD = 17, SW = 32 * SD;
+  static_assert(8 * SW <= NR * S && (NS - 8) * SW <= NR * S, "stages must fit in slots 0 and 2");
+  double *stage = w < 8 ? &sh.slot[0][0] + SW * w : &sh.slot[2][0] + SW * (w - 8);
   dbl4 acc[16];
   {
     const int rr = lane >> 1, cb = 16 * w + 8 * (lane & 1);
     const int jy0 = cb / PI, jx0 = cb - jy0 * PI;     // interior coordinates of column cb
-    double *srow = stage + rr * 16 + 8 * (lane & 1);
+    double *srow = stage + rr * SD + 8 * (lane & 1);
 #pragma unroll
     for (int tc = 0; tc < 8; ++tc) {
       const int row = 32 * tc + rr;
@@ -508,8 +517,8 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
         int jy = jy0 + 1, jx = jx0 + 1;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const double dy = Dh[iy * P + jy], dx = Dh[ix * P + jx];
-          const double d2y = Dh2[iy * P + jy], d2x = Dh2[ix * P + jx];
+          const double dy = Dh[iy * DS + jy], dx = Dh[ix * DS + jx];
+          const double d2y = Dh2[iy * DS + jy], d2x = Dh2[ix * DS + jx];
           double v = cxy * dy * dx;
           v += iy == jy ? fma(cxx, d2x, cx * dx) : 0.0;
           v += ix == jx ? fma(cyy, d2y, cy * dy) : 0.0;
@@ -528,8 +537,8 @@ __global__ __launch_bounds__(gjb::NT) void gjb_leaf_kernel(
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        acc[2 * tc][v] = stage[(4 * v + g) * 16 + n];
-        acc[2 * tc + 1][v] = stage[(16 + 4 * v + g) * 16 + n];
+        acc[2 * tc][v] = stage[(4 * v + g) * SD + n];
+        acc[2 * tc + 1][v] = stage[(16 + 4 * v + g) * SD + n];
       }
       __builtin_amdgcn_wave_barrier();
     }
