@@ -116,10 +116,21 @@ __device__ __forceinline__ void sweep_step(double (&x)[4][NC], unsigned &umask, 
   if (!ok && bad == 0) bad = isfinite(piv) ? (k0 + C + 1) : -(k0 + C + 1);
 }
 
+// Per-lane LDS addresses (lane + 64 i rows of the tables and slots) cost one
+// vector operation each, but the compiler hoists them out of the panel loop
+// and, short of registers there, keeps them in scratch memory, so that every
+// sweep waits for their reloads.  A lane index made opaque at the start of a
+// step keeps them local to it.
+__device__ __forceinline__ int fresh_lane(int lane) {
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
+
 // Record steps k0 .. k0 + NC - 1 of a finished sweep in LDS.
 template <int NC>
 __device__ __forceinline__ void sweep_log(int k0, int lane, int myr, double mysig, int bad,
                                           Shared &sh) {
+  lane = fresh_lane(lane);
   if (lane < NC) {
     sh.stepof[myr] = k0 + lane;
     sh.pivrow[k0 + lane] = myr;
@@ -176,6 +187,7 @@ __device__ __forceinline__ void post(int &flag, int v, int lane) {
 }
 
 __device__ __forceinline__ unsigned used_rows(int lane, const Shared &sh) {
+  lane = fresh_lane(lane);
   unsigned umask = 0u;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -190,6 +202,7 @@ __device__ __forceinline__ unsigned used_rows(int lane, const Shared &sh) {
 // (rows R zeroed) + P W, with W the old rows R (copied to wbuf first).
 __device__ __forceinline__ void apply_half(double *sl, int from, int to, int k0, int lane,
                                            Shared &sh) {
+  lane = fresh_lane(lane);
   {
     const int k = lane >> 3, c = lane & 7;
     sh.wbuf[lane] = sl[sh.pivrow[k0 + k] * S + to + c];
@@ -233,6 +246,7 @@ __device__ __forceinline__ void apply_half(double *sl, int from, int to, int k0,
 // Sweep of 8 panel columns COL0 .. COL0 + 7 of slot sl in registers (steps
 // k0 .. k0 + 7).
 __device__ __forceinline__ void sweep_half(double *sl, int col0, int k0, int lane, Shared &sh) {
+  lane = fresh_lane(lane);
   double x[4][8];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -274,6 +288,7 @@ __device__ __forceinline__ void sweep_half(double *sl, int col0, int k0, int lan
 // P1 the second half after L1.  Every other column block then applies L0 and
 // L1 in turn, and the owner applies L1 to P0 in the next round.
 __device__ __forceinline__ void sweep_strip(dbl4 (&acc)[16], int q, int lane, Shared &sh) {
+  lane = fresh_lane(lane);
   double *sl = sh.slot[q % NSLOT];
   const int g = lane >> 4, n = lane & 15;
 #pragma unroll
@@ -378,6 +393,7 @@ __device__ __forceinline__ void update_strip4(dbl4 (&acc)[16], int lane, double 
 // Tail <- L1 (L0 tail) for panel q, on the vector ALU by the wavefront that
 // owns panel q (it has no strip update in that round).
 __device__ __forceinline__ void update_tail(int q, int lane, Shared &sh) {
+  lane = fresh_lane(lane);
   const double *sl = sh.slot[q % NSLOT];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
