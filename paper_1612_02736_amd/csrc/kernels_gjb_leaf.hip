@@ -119,18 +119,21 @@ __device__ __forceinline__ void sweep_step(double (&x)[4][NC], unsigned &umask, 
 // Per-lane LDS addresses (lane + 64 i rows of the tables and slots) cost one
 // vector operation each, but the compiler hoists them out of the panel loop
 // and, short of registers there, keeps them in scratch memory, so that every
-// sweep waits for their reloads.  A lane index made opaque at the start of a
-// step keeps them local to it.
-__device__ __forceinline__ int fresh_lane(int lane) {
-  asm volatile("" : "+v"(lane));
-  return lane;
+// sweep waits for their reloads.  The lane index read afresh from the
+// hardware at the start of a step (the count of lanes below this one, in an
+// instruction the compiler may not move or merge) keeps them local to it,
+// with nothing live across the loop.
+__device__ __forceinline__ int lane_now() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
 }
 
 // Record steps k0 .. k0 + NC - 1 of a finished sweep in LDS.
 template <int NC>
 __device__ __forceinline__ void sweep_log(int k0, int lane, int myr, double mysig, int bad,
                                           Shared &sh) {
-  lane = fresh_lane(lane);
+  lane = lane_now();
   if (lane < NC) {
     sh.stepof[myr] = k0 + lane;
     sh.pivrow[k0 + lane] = myr;
@@ -187,7 +190,7 @@ __device__ __forceinline__ void post(int &flag, int v, int lane) {
 }
 
 __device__ __forceinline__ unsigned used_rows(int lane, const Shared &sh) {
-  lane = fresh_lane(lane);
+  lane = lane_now();
   unsigned umask = 0u;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -202,7 +205,7 @@ __device__ __forceinline__ unsigned used_rows(int lane, const Shared &sh) {
 // (rows R zeroed) + P W, with W the old rows R (copied to wbuf first).
 __device__ __forceinline__ void apply_half(double *sl, int from, int to, int k0, int lane,
                                            Shared &sh) {
-  lane = fresh_lane(lane);
+  lane = lane_now();
   {
     const int k = lane >> 3, c = lane & 7;
     sh.wbuf[lane] = sl[sh.pivrow[k0 + k] * S + to + c];
@@ -246,7 +249,7 @@ __device__ __forceinline__ void apply_half(double *sl, int from, int to, int k0,
 // Sweep of 8 panel columns COL0 .. COL0 + 7 of slot sl in registers (steps
 // k0 .. k0 + 7).
 __device__ __forceinline__ void sweep_half(double *sl, int col0, int k0, int lane, Shared &sh) {
-  lane = fresh_lane(lane);
+  lane = lane_now();
   double x[4][8];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -288,7 +291,7 @@ __device__ __forceinline__ void sweep_half(double *sl, int col0, int k0, int lan
 // P1 the second half after L1.  Every other column block then applies L0 and
 // L1 in turn, and the owner applies L1 to P0 in the next round.
 __device__ __forceinline__ void sweep_strip(dbl4 (&acc)[16], int q, int lane, Shared &sh) {
-  lane = fresh_lane(lane);
+  lane = lane_now();
   double *sl = sh.slot[q % NSLOT];
   const int g = lane >> 4, n = lane & 15;
 #pragma unroll
@@ -301,10 +304,11 @@ __device__ __forceinline__ void sweep_strip(dbl4 (&acc)[16], int q, int lane, Sh
   apply_half(sl, 0, 8, 16 * q, lane, sh);
   sweep_half(sl, 8, 16 * q + 8, lane, sh);
   post(sh.ready, 2 * q + 1, lane);
+  const int lane2 = lane_now(), g2 = lane2 >> 4, n2 = lane2 & 15;
 #pragma unroll
   for (int t = 0; t < 16; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[t][v] = sl[(16 * t + 4 * v + g) * S + n];
+    for (int v = 0; v < 4; ++v) acc[t][v] = sl[(16 * t + 4 * v + g2) * S + n2];
 }
 
 // Rows R of steps k0 .. k0 + K - 1 in this wavefront's strip: copy them to
@@ -314,6 +318,7 @@ __device__ __forceinline__ void sweep_strip(dbl4 (&acc)[16], int q, int lane, Sh
 template <int K, bool LEFT = false>
 __device__ __forceinline__ void gather_w(dbl4 (&acc)[16], int k0, int lane, double *wt,
                                          const Shared &sh) {
+  lane = lane_now();
   const int g = lane >> 4, n = lane & 15;
   unsigned long long U = 0ull;
 #pragma unroll
@@ -343,6 +348,7 @@ __device__ __forceinline__ void gather_w(dbl4 (&acc)[16], int k0, int lane, doub
 // per lane.  Two tiles at a time, their MFMA chains interleaved.
 __device__ __forceinline__ void update_half(dbl4 (&acc)[16], const double *sl, int col0, int lane,
                                             const double *wt) {
+  lane = lane_now();
   const int g = lane >> 4, n = lane & 15;
   const double2 b = *reinterpret_cast<const double2 *>(wt + n * WS + 2 * g);
 #pragma unroll
@@ -381,6 +387,7 @@ __device__ __forceinline__ void owner_fixup(dbl4 (&acc)[16], int q, int lane, do
 // The last panel (tail columns, steps 192 .. 195, in slot 0): one MFMA step.
 __device__ __forceinline__ void update_strip4(dbl4 (&acc)[16], int lane, double *wt,
                                               const Shared &sh) {
+  lane = lane_now();
   const int g = lane >> 4, n = lane & 15;
   gather_w<TCN>(acc, TC0, lane, wt, sh);
   const double b = wt[n * WS + g];
@@ -393,7 +400,7 @@ __device__ __forceinline__ void update_strip4(dbl4 (&acc)[16], int lane, double 
 // Tail <- L1 (L0 tail) for panel q, on the vector ALU by the wavefront that
 // owns panel q (it has no strip update in that round).
 __device__ __forceinline__ void update_tail(int q, int lane, Shared &sh) {
-  lane = fresh_lane(lane);
+  lane = lane_now();
   const double *sl = sh.slot[q % NSLOT];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -431,6 +438,7 @@ __device__ __forceinline__ void update_tail(int q, int lane, Shared &sh) {
 
 // Sweep of the tail (steps 192 .. 195), the last panel (index NS).
 __device__ __forceinline__ void sweep_tail(int lane, Shared &sh) {
+  lane = lane_now();
   double x[4][TCN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
