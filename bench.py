@@ -50,9 +50,9 @@ KERNEL_SOURCES = {"gemm": ["kernels_gemm.hip", "kernel_util.hpp"],
                   "gj_panel": ["kernels_gj_blocked.hip", "gj_core.hpp", "kernel_util.hpp"],
                   "apply": ["kernels_mfma.hip", "kernels_apply.hip", "kernel_util.hpp"]}
 MEASURED_TRAFFIC = {
-    # gjb_leaf_kernel: FETCH_SIZE 219,162 KiB x 2.000 + WRITE_SIZE 2,097,444 KiB
+    # gjb_leaf_kernel: FETCH_SIZE 73,281 KiB x 2.000 + WRITE_SIZE 1,736,417 KiB
     # x 1.000 per launch (64 x 64 leaves, p = 16)
-    "gj_leaf[0]": ("5b9437320eeb139a", 2596.6e6),
+    "gj_leaf[0]": ("bc2b0ff3a2829fce", 1928.2e6),
     # gj_level_kernel + gj_level_rest_kernel (the five level launches of a
     # 64 x 64-leaf factorization): FETCH_SIZE 26,371 KiB x 2.000 + WRITE_SIZE
     # 11,559 KiB x 1.000 per level
